@@ -1,0 +1,216 @@
+"""ctypes front end of the C oracle (oracle/zg_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Builds the oracle with gcc (-O2 -ffp-contract=off)
+into oracle/libzg_oracle.so and exposes numpy-returning wrappers.  The table it
+uses is the stored 60-digit oracle table (oracle/table_b128.json), never the
+product library's.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import table_mp
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "zg_oracle.c")
+LIB = os.path.join(HERE, "libzg_oracle.so")
+
+SM64 = 1
+LCG48 = 2
+DMAX = 256
+
+
+def build(force=True):
+    """Compile the oracle shared library (always recompiles when force)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-pthread", SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class OrcTable(ctypes.Structure):
+    _fields_ = [
+        ("r", ctypes.c_double),
+        ("W", ctypes.c_double * 128),
+        ("y", ctypes.c_double * 128),
+        ("dy", ctypes.c_double * 128),
+        ("w53", ctypes.c_double * 128),
+        ("w24d", ctypes.c_double * 128),
+        ("w24", ctypes.c_float * 128),
+        ("k53", ctypes.c_uint64 * 128),
+        ("k24", ctypes.c_uint32 * 128),
+    ]
+
+
+_lib = None
+_table = None
+_table_dict = None
+
+u64 = ctypes.c_uint64
+u32 = ctypes.c_uint32
+i32 = ctypes.c_int
+vp = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=False)
+        L = ctypes.CDLL(LIB)
+        L.orc_sm64_word.argtypes = [u64, u32, u64, u32]
+        L.orc_sm64_word.restype = u64
+        L.orc_lcg_word.argtypes = [u64, u32, u64, u32]
+        L.orc_lcg_word.restype = u64
+        L.orc_lcg_state.argtypes = [u64, u64]
+        L.orc_lcg_state.restype = u64
+        L.orc_lcg_state0.argtypes = [u64]
+        L.orc_lcg_state0.restype = u64
+        L.orc_lcg_step.argtypes = [u64]
+        L.orc_lcg_step.restype = u64
+        L.orc_lcg_affine.argtypes = [u64, vp, vp]
+        L.orc_lcg_affine.restype = None
+        L.orc_lcg_seq_doubles.argtypes = [u64, u64, vp]
+        L.orc_lcg_seq_doubles.restype = None
+        L.orc_lcg_seq_ints.argtypes = [u64, u64, vp]
+        L.orc_lcg_seq_ints.restype = None
+        L.orc_zig_f64.argtypes = [vp, i32, u64, u32, u64, u32, vp]
+        L.orc_zig_f64.restype = ctypes.c_double
+        L.orc_decide_word.argtypes = [vp, u64, vp]
+        L.orc_decide_word.restype = i32
+        L.orc_polar_core.argtypes = [ctypes.c_double, ctypes.c_double, vp, vp]
+        L.orc_polar_core.restype = i32
+        L.orc_fill_f64.argtypes = [vp, i32, u64, u32, u64, u64, u32, vp, vp, i32]
+        L.orc_fill_f64.restype = u64
+        L.orc_fill_f32.argtypes = [vp, i32, u64, u32, u64, u64, u32, vp, vp, vp, i32]
+        L.orc_fill_f32.restype = u64
+        L.orc_fill_polar.argtypes = [i32, u64, u32, u64, u64, u32, vp, vp, i32]
+        L.orc_fill_polar.restype = u64
+        L.orc_mutate.argtypes = [vp, i32, u64, u32, u64, u64, u32, ctypes.c_double, vp, vp, i32]
+        L.orc_mutate.restype = u64
+        L.orc_words.argtypes = [i32, u64, u32, u32, u64, u64, vp]
+        L.orc_words.restype = None
+        _lib = L
+    return _lib
+
+
+def table_dict():
+    """The stored oracle table (correctly rounded entries) as a dict."""
+    global _table_dict
+    if _table_dict is None:
+        _table_dict = table_mp.load_table()
+    return _table_dict
+
+
+def table():
+    """The stored oracle table as the C struct."""
+    global _table
+    if _table is None:
+        t = table_dict()
+        T = OrcTable()
+        T.r = t["r"]
+        for i in range(128):
+            T.W[i] = t["W"][i]
+            T.y[i] = t["y"][i]
+            T.dy[i] = t["dy"][i]
+            T.w53[i] = t["w53"][i]
+            T.w24d[i] = t["w24d"][i]
+            T.w24[i] = t["w24f"][i] * 2.0 ** -24
+            T.k53[i] = t["k53"][i]
+            T.k24[i] = t["k24"][i]
+        _table = T
+    return _table
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _threads(nthreads):
+    return nthreads if nthreads else min(os.cpu_count() or 1, 64)
+
+
+def word(kind, seed, s, v, d):
+    L = lib()
+    f = L.orc_lcg_word if kind == LCG48 else L.orc_sm64_word
+    return int(f(seed & (2**64 - 1), s, v, d))
+
+
+def words(kind, seed, s, d, first, n):
+    out = np.empty(n, dtype=np.uint64)
+    lib().orc_words(kind, seed & (2**64 - 1), s, d, first, n, _p(out))
+    return out
+
+
+def lcg_seq_doubles(seed, n):
+    out = np.empty(n, dtype=np.uint64)
+    lib().orc_lcg_seq_doubles(seed & (2**64 - 1), n, _p(out))
+    return out
+
+
+def lcg_seq_ints(seed, n):
+    out = np.empty(n, dtype=np.int32)
+    lib().orc_lcg_seq_ints(seed & (2**64 - 1), n, _p(out))
+    return out
+
+
+def lcg_affine(k):
+    A = ctypes.c_uint64()
+    C = ctypes.c_uint64()
+    lib().orc_lcg_affine(k, ctypes.byref(A), ctypes.byref(C))
+    return A.value, C.value
+
+
+def fill_f64(kind, seed, s, first, n, dmax=DMAX, nthreads=0):
+    """FP64 ziggurat variates first..first+n-1; returns (values, outcome codes, errors)."""
+    out = np.empty(n, dtype=np.float64)
+    cls = np.empty(n, dtype=np.uint8)
+    errs = lib().orc_fill_f64(ctypes.byref(table()), kind, seed & (2**64 - 1), s, first, n,
+                              dmax, _p(out), _p(cls), _threads(nthreads))
+    return out, cls, int(errs)
+
+
+def fill_f32(kind, seed, s, first, n, dmax=DMAX, nthreads=0):
+    """FP32 ziggurat variates; returns (values f32, FP64 value of the same
+    decision, outcome codes, errors)."""
+    out = np.empty(n, dtype=np.float32)
+    out64 = np.empty(n, dtype=np.float64)
+    cls = np.empty(n, dtype=np.uint8)
+    errs = lib().orc_fill_f32(ctypes.byref(table()), kind, seed & (2**64 - 1), s, first, n,
+                              dmax, _p(out), _p(out64), _p(cls), _threads(nthreads))
+    return out, out64, cls, int(errs)
+
+
+def fill_polar(kind, seed, s, first, n, dmax=DMAX, nthreads=0):
+    out = np.empty(n, dtype=np.float64)
+    cls = np.empty(n, dtype=np.uint8)
+    errs = lib().orc_fill_polar(kind, seed & (2**64 - 1), s, first, n, dmax, _p(out),
+                                _p(cls), _threads(nthreads))
+    return out, cls, int(errs)
+
+
+def mutate(x, kind, seed, s, first, sigma, dmax=DMAX, nthreads=0):
+    """Returns a mutated copy of x (float64 array) and the outcome codes."""
+    y = np.array(x, dtype=np.float64, copy=True)
+    cls = np.empty(y.size, dtype=np.uint8)
+    errs = lib().orc_mutate(ctypes.byref(table()), kind, seed & (2**64 - 1), s, first, y.size,
+                            dmax, sigma, _p(y), _p(cls), _threads(nthreads))
+    return y, cls, int(errs)
+
+
+def decide_word(W):
+    x = ctypes.c_double()
+    c = lib().orc_decide_word(ctypes.byref(table()), W, ctypes.byref(x))
+    return int(c), x.value
+
+
+def polar_core(u1, u2):
+    o1 = ctypes.c_double()
+    o2 = ctypes.c_double()
+    ok = lib().orc_polar_core(u1, u2, ctypes.byref(o1), ctypes.byref(o2))
+    return bool(ok), o1.value, o2.value

@@ -1,0 +1,449 @@
+/*
+ * zg_oracle.c -- plain, slow, scalar CPU oracle for the ziggurat Gaussian path.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline of the benchmark.  It shares no code with the product library.
+ * Build: gcc -O2 -ffp-contract=off (no FMA contraction), glibc libm.
+ *
+ * What it follows:
+ *  - The original ziggurat that the paper ports from GSL (Section 1, Section 2
+ *    "Ziggurat", after Marsaglia-Tsang 2000 and Leong 2005): 128 equal-area
+ *    layers, a fast accept inside the inner box of a layer, a wedge test
+ *    against exp(-x^2/2), and sampling beyond r for the base layer.  The table
+ *    is an input (correctly rounded values computed in 60-digit arithmetic).
+ *  - The polar method (Section 1; Section 2 "Java 17" for Random/TLR):
+ *    v = 2U-1 pairs, reject s >= 1 or s == 0, multiplier sqrt(-2 ln s / s).
+ *  - The uniform sources of Section 2: SplittableRandom (SplitMix64) and
+ *    java.util.Random (48-bit LCG, a = 0x5DEECE66D, c = 0xB), each made
+ *    index-addressable: word(seed, stream s, variate v, draw d).  The LCG
+ *    windows are spaced by odd numbers of doubles (see orc_lcg_word).
+ *  - Gaussian mutation (Section 1): x <- x + sigma * z.
+ *
+ * Readings where the paper is silent (each one is listed in the design notes):
+ *  - base layer area v = r f(r) + f(r)/r (exponential majorant), a tail
+ *    rejection restarts the whole attempt;
+ *  - the tail draw a = -log(U1+)/r, x = r + a, accept iff U2 < exp(-a^2/2);
+ *  - word decode: layer = W>>57, sign = bit 56, j = bits 3..55, U = (W>>11)2^-53,
+ *    U+ = ((W>>11)+1) 2^-53;
+ *  - fast accept is the integer test j < k53[i], x = (double)j * w53[i];
+ *  - wedge: y = y[i-1] + U dy[i], accept iff y < exp(-0.5 (x x));
+ *  - a wedge rejection restarts at draw d+2, a tail rejection at d+3; words
+ *    with draw index >= dmax (256 by default) are never used: the variate
+ *    becomes the canonical quiet NaN and the error count is raised.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <string.h>
+
+#define ORC_SM64 1
+#define ORC_LCG48 2
+
+typedef struct {
+  double r;
+  double W[128];    /* layer widths, RN64 */
+  double y[128];    /* f(b_i), y[127] = 1 */
+  double dy[128];   /* y[i] - y[i-1] */
+  double w53[128];  /* W[i] * 2^-53 */
+  double w24d[128]; /* W[i] * 2^-24 (FP64, slow path of the FP32 mode) */
+  float w24[128];   /* RN32(W[i]) * 2^-24 */
+  uint64_t k53[128];
+  uint32_t k24[128];
+} orc_table;
+
+/* ---------------------------------------------------------------- uniforms */
+
+/* SplitMix64 finaliser (Steele, Lea, Flood 2014; SplittableRandom.mix64). */
+static uint64_t orc_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* SplittableRandom(seed): the k-th nextLong (0-based) is mix64(seed + (k+1)gamma).
+ * Index-keyed: counter = 1 + s 2^48 + d 2^40 + v  (s < 2^16, d < 2^8, v < 2^40). */
+uint64_t orc_sm64_word(uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  uint64_t ctr = 1 + ((uint64_t)s << 48) + ((uint64_t)d << 40) + v;
+  return orc_mix64(seed + 0x9E3779B97F4A7C15ULL * ctr);
+}
+
+#define LCG_A 0x5DEECE66DULL
+#define LCG_C 0xBULL
+#define M48 ((1ULL << 48) - 1)
+
+/* java.util.Random initial scramble. */
+uint64_t orc_lcg_state0(uint64_t seed) { return (seed ^ LCG_A) & M48; }
+
+/* One LCG step S <- a S + c (mod 2^48). */
+uint64_t orc_lcg_step(uint64_t S) { return (LCG_A * S + LCG_C) & M48; }
+
+/* The affine map of k steps, S -> A S + C, by repeated squaring of (a, c).
+ * Composition of two maps (A1,C1) then (A2,C2) is (A2 A1, A2 C1 + C2). */
+void orc_lcg_affine(uint64_t k, uint64_t *A_out, uint64_t *C_out) {
+  uint64_t A = 1, C = 0;            /* identity */
+  uint64_t a = LCG_A, c = LCG_C;    /* one step */
+  while (k) {
+    if (k & 1) {
+      C = (a * C + c) & M48;
+      A = (a * A) & M48;
+    }
+    c = (a * c + c) & M48;
+    a = (a * a) & M48;
+    k >>= 1;
+  }
+  *A_out = A;
+  *C_out = C;
+}
+
+/* State after k steps from state0. */
+uint64_t orc_lcg_state(uint64_t seed, uint64_t k) {
+  uint64_t A, C;
+  orc_lcg_affine(k, &A, &C);
+  return (A * orc_lcg_state0(seed) + C) & M48;
+}
+
+/* Index-keyed nextDouble of Random(seed).  Double index
+ *   m = s * LCG_STREAM + d * LCG_WINDOW + v,  s < 2^8, d < 2^8, v < LCG_WINDOW,
+ * consumes LCG steps 2m+1 and 2m+2 exactly as nextDouble does (26 high bits,
+ * then 27), giving M = hi26 2^27 + lo27; the 64-bit word is M << 11 so that
+ * U = (W >> 11) 2^-53 is Random.nextDouble.  Stream 0, draw 0 is the sequential
+ * stream.  Both spacings are odd numbers of doubles: a jump of 2K steps then
+ * has multiplier a^(2K) = 1 mod 8 only, whose 2-D lattice is as fine as that of
+ * consecutive doubles.  A power-of-two spacing 2^k would give a multiplier
+ * = 1 mod 2^(k+3) and nearly identical words across windows or streams. */
+#define LCG_WINDOW 2147483547ULL        /* 2^31 - 101 */
+#define LCG_STREAM 549755793563ULL      /* 2^39 - 20325 >= 256 LCG_WINDOW */
+uint64_t orc_lcg_word(uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  uint64_t m = (uint64_t)s * LCG_STREAM + (uint64_t)d * LCG_WINDOW + v;
+  uint64_t S1 = orc_lcg_state(seed, 2 * m + 1);
+  uint64_t S2 = orc_lcg_step(S1);
+  uint64_t M = ((S1 >> 22) << 27) + (S2 >> 21);
+  return M << 11;
+}
+
+/* Sequential Random(seed).nextDouble() numerators M (53 bits), n of them:
+ * the plain sequential generator, used to check the index-keyed words. */
+void orc_lcg_seq_doubles(uint64_t seed, uint64_t n, uint64_t *out) {
+  uint64_t S = orc_lcg_state0(seed);
+  for (uint64_t m = 0; m < n; ++m) {
+    S = orc_lcg_step(S);
+    uint64_t hi = S >> 22;
+    S = orc_lcg_step(S);
+    uint64_t lo = S >> 21;
+    out[m] = (hi << 27) + lo;
+  }
+}
+
+/* Sequential Random(seed).nextInt() values (next(32) as signed 32-bit). */
+void orc_lcg_seq_ints(uint64_t seed, uint64_t n, int32_t *out) {
+  uint64_t S = orc_lcg_state0(seed);
+  for (uint64_t m = 0; m < n; ++m) {
+    S = orc_lcg_step(S);
+    out[m] = (int32_t)(uint32_t)(S >> 16);
+  }
+}
+
+uint64_t orc_word(int kind, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  return kind == ORC_LCG48 ? orc_lcg_word(seed, s, v, d) : orc_sm64_word(seed, s, v, d);
+}
+
+static double u53(uint64_t W) { return (double)(W >> 11) * 0x1p-53; }         /* [0,1) */
+static double u53p(uint64_t W) { return (double)((W >> 11) + 1) * 0x1p-53; }  /* (0,1] */
+
+static double nan64(void) {
+  uint64_t b = 0x7FF8000000000000ULL;
+  double x;
+  memcpy(&x, &b, 8);
+  return x;
+}
+static float nan32(void) {
+  uint32_t b = 0x7FC00000u;
+  float x;
+  memcpy(&x, &b, 4);
+  return x;
+}
+
+/* ------------------------------------------------------- ziggurat pieces */
+
+/* Outcome codes: low 2 bits = path of the accepted attempt (0 fast, 1 wedge,
+ * 2 tail, 3 budget exhausted); bits 2..7 = min(attempts - 1, 63). */
+static uint8_t outcome(int path, int attempts) {
+  int a = attempts - 1;
+  if (a > 63) a = 63;
+  return (uint8_t)(path | (a << 2));
+}
+
+/* Slow part of one attempt for layer i at draw d (the first word failed the
+ * fast test).  x is the candidate from the first word (wedge only).  Returns
+ * 1 and sets *xo on acceptance, 0 on rejection, -1 if the budget is hit;
+ * *next_d receives the draw index of the next attempt. */
+static int slow_step(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t v,
+                     uint32_t d, uint32_t dmax, int i, double x, double *xo, uint32_t *next_d,
+                     int *path) {
+  if (i == 0) {
+    if (d + 2 >= dmax) return -1;
+    double u1 = u53p(orc_word(kind, seed, s, v, d + 1));
+    double u2 = u53(orc_word(kind, seed, s, v, d + 2));
+    double a = -log(u1) / T->r;
+    double xt = T->r + a;
+    *next_d = d + 3;
+    *path = 2;
+    if (u2 < exp(-0.5 * (a * a))) {
+      *xo = xt;
+      return 1;
+    }
+    return 0;
+  }
+  if (d + 1 >= dmax) return -1;
+  double u = u53(orc_word(kind, seed, s, v, d + 1));
+  double y = T->y[i - 1] + u * T->dy[i];
+  *next_d = d + 2;
+  *path = 1;
+  if (y < exp(-0.5 * (x * x))) {
+    *xo = x;
+    return 1;
+  }
+  return 0;
+}
+
+/* One FP64 standard normal for index v. */
+double orc_zig_f64(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t v,
+                   uint32_t dmax, uint8_t *cls) {
+  uint32_t d = 0;
+  int attempts = 0;
+  for (;;) {
+    if (d >= dmax) {
+      *cls = outcome(3, attempts + 1);
+      return nan64();
+    }
+    uint64_t W = orc_word(kind, seed, s, v, d);
+    int i = (int)(W >> 57);
+    int neg = (int)((W >> 56) & 1);
+    uint64_t j = (W >> 3) & ((1ULL << 53) - 1);
+    double x = (double)j * T->w53[i];
+    attempts++;
+    if (j < T->k53[i]) {
+      *cls = outcome(0, attempts);
+      return neg ? -x : x;
+    }
+    double xo;
+    uint32_t nd;
+    int path;
+    int rc = slow_step(T, kind, seed, s, v, d, dmax, i, x, &xo, &nd, &path);
+    if (rc < 0) {
+      *cls = outcome(3, attempts);
+      return nan64();
+    }
+    if (rc == 1) {
+      *cls = outcome(path, attempts);
+      return neg ? -xo : xo;
+    }
+    d = nd;
+  }
+}
+
+/* One attempt's class for a crafted first word (layer, sign, j decoded from W):
+ * 0 fast, 1 wedge, 2 tail; *x is the first-word candidate (j * w53[i], signed). */
+int orc_decide_word(const orc_table *T, uint64_t W, double *x) {
+  int i = (int)(W >> 57);
+  int neg = (int)((W >> 56) & 1);
+  uint64_t j = (W >> 3) & ((1ULL << 53) - 1);
+  double xv = (double)j * T->w53[i];
+  *x = neg ? -xv : xv;
+  if (j < T->k53[i]) return 0;
+  return i == 0 ? 2 : 1;
+}
+
+/* FP32 output mode.  The attempt word is 32 bits: for the SplitMix64 kind the
+ * first attempt of variates 2t and 2t+1 takes the high and low halves of
+ * W(s, t, 0); every other attempt (and every LCG attempt) takes hi32(W(s,v,d)).
+ * Decode: layer = u>>25, sign = bit 24, j = low 24 bits.  Fast path in FP32:
+ * fl32(fl32(j) * w24[i]); wedge and tail in FP64 with x = j * w24d[i];
+ * out = fl32(+-x).  *x64 receives the FP64 value of the same decision
+ * (the fast path evaluated in FP64), for the error statement. */
+float orc_zig_f32(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t v,
+                  uint32_t dmax, uint8_t *cls, double *x64) {
+  uint32_t d = 0;
+  int attempts = 0;
+  for (;;) {
+    if (d >= dmax) {
+      *cls = outcome(3, attempts + 1);
+      *x64 = nan64();
+      return nan32();
+    }
+    uint32_t u;
+    if (d == 0 && kind == ORC_SM64) {
+      uint64_t W = orc_sm64_word(seed, s, v >> 1, 0);
+      u = (v & 1) ? (uint32_t)W : (uint32_t)(W >> 32);
+    } else {
+      u = (uint32_t)(orc_word(kind, seed, s, v, d) >> 32);
+    }
+    int i = (int)(u >> 25);
+    int neg = (int)((u >> 24) & 1);
+    uint32_t j = u & 0xFFFFFFu;
+    attempts++;
+    if (j < T->k24[i]) {
+      float xf = (float)j * T->w24[i];
+      double xd = (double)j * T->w24d[i];
+      *cls = outcome(0, attempts);
+      *x64 = neg ? -xd : xd;
+      return neg ? -xf : xf;
+    }
+    double x = (double)j * T->w24d[i];
+    double xo;
+    uint32_t nd;
+    int path;
+    int rc = slow_step(T, kind, seed, s, v, d, dmax, i, x, &xo, &nd, &path);
+    if (rc < 0) {
+      *cls = outcome(3, attempts);
+      *x64 = nan64();
+      return nan32();
+    }
+    if (rc == 1) {
+      double sx = neg ? -xo : xo;
+      *cls = outcome(path, attempts);
+      *x64 = sx;
+      return (float)sx;
+    }
+    d = nd;
+  }
+}
+
+/* ------------------------------------------------------------------ polar */
+
+/* One polar attempt from two uniforms in [0,1) (Knuth's polar method as in
+ * java.util.Random.nextGaussian): returns 1 and the pair on acceptance. */
+int orc_polar_core(double u1, double u2, double *o1, double *o2) {
+  double v1 = 2.0 * u1 - 1.0;
+  double v2 = 2.0 * u2 - 1.0;
+  double s = v1 * v1 + v2 * v2;
+  if (s >= 1.0 || s == 0.0) return 0;
+  double m = sqrt(-2.0 * log(s) / s);
+  *o1 = v1 * m;
+  *o2 = v2 * m;
+  return 1;
+}
+
+/* Pair p of stream s: attempt a uses draws 2a and 2a+1 of index p. */
+static int polar_pair(int kind, uint64_t seed, uint32_t s, uint64_t p, uint32_t dmax,
+                      double *o1, double *o2, int *attempts) {
+  for (uint32_t a = 0;; ++a) {
+    if (2 * a + 1 >= dmax) {
+      *attempts = (int)a + 1;
+      *o1 = *o2 = nan64();
+      return 0;
+    }
+    double u1 = u53(orc_word(kind, seed, s, p, 2 * a));
+    double u2 = u53(orc_word(kind, seed, s, p, 2 * a + 1));
+    if (orc_polar_core(u1, u2, o1, o2)) {
+      *attempts = (int)a + 1;
+      return 1;
+    }
+  }
+}
+
+/* ------------------------------------------------------------ bulk fills */
+
+typedef struct {
+  const orc_table *T;
+  int op; /* 0 zig f64, 1 zig f32, 2 polar f64, 3 mutate f64 */
+  int kind;
+  uint64_t seed;
+  uint32_t s;
+  uint64_t first;
+  uint64_t lo, hi;
+  uint32_t dmax;
+  double sigma;
+  void *out;
+  double *out64;
+  uint8_t *cls;
+  uint64_t errors;
+} orc_job;
+
+static void *run_job(void *arg) {
+  orc_job *J = (orc_job *)arg;
+  uint64_t errs = 0;
+  for (uint64_t k = J->lo; k < J->hi; ++k) {
+    uint64_t v = J->first + k;
+    uint8_t c = 0;
+    if (J->op == 0) {
+      ((double *)J->out)[k] = orc_zig_f64(J->T, J->kind, J->seed, J->s, v, J->dmax, &c);
+    } else if (J->op == 1) {
+      double x64;
+      ((float *)J->out)[k] = orc_zig_f32(J->T, J->kind, J->seed, J->s, v, J->dmax, &c, &x64);
+      if (J->out64) J->out64[k] = x64;
+    } else if (J->op == 2) {
+      double o1, o2;
+      int att;
+      int ok = polar_pair(J->kind, J->seed, J->s, v >> 1, J->dmax, &o1, &o2, &att);
+      ((double *)J->out)[k] = (v & 1) ? o2 : o1;
+      c = (uint8_t)(ok ? ((att - 1 > 63 ? 63 : att - 1) << 2) : (3 | ((att - 1 > 63 ? 63 : att - 1) << 2)));
+    } else {
+      double z = orc_zig_f64(J->T, J->kind, J->seed, J->s, v, J->dmax, &c);
+      double *x = (double *)J->out;
+      x[k] = x[k] + J->sigma * z;
+    }
+    if ((c & 3) == 3) errs++;
+    if (J->cls) J->cls[k] = c;
+  }
+  J->errors = errs;
+  return 0;
+}
+
+/* Runs an op over [0, n) split into nthreads contiguous chunks; returns the
+ * number of variates that exhausted the draw budget. */
+static uint64_t run_split(orc_job proto, uint64_t n, int nthreads) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  if ((uint64_t)nthreads > n) nthreads = n ? (int)n : 1;
+  pthread_t th[256];
+  orc_job jobs[256];
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t] = proto;
+    jobs[t].lo = n * (uint64_t)t / (uint64_t)nthreads;
+    jobs[t].hi = n * (uint64_t)(t + 1) / (uint64_t)nthreads;
+  }
+  if (nthreads == 1) {
+    run_job(&jobs[0]);
+    return jobs[0].errors;
+  }
+  for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], 0, run_job, &jobs[t]);
+  uint64_t errs = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    pthread_join(th[t], 0);
+    errs += jobs[t].errors;
+  }
+  return errs;
+}
+
+uint64_t orc_fill_f64(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t first,
+                      uint64_t n, uint32_t dmax, double *out, uint8_t *cls, int nthreads) {
+  orc_job j = {T, 0, kind, seed, s, first, 0, 0, dmax, 0.0, out, 0, cls, 0};
+  return run_split(j, n, nthreads);
+}
+
+uint64_t orc_fill_f32(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t first,
+                      uint64_t n, uint32_t dmax, float *out, double *out64, uint8_t *cls,
+                      int nthreads) {
+  orc_job j = {T, 1, kind, seed, s, first, 0, 0, dmax, 0.0, out, out64, cls, 0};
+  return run_split(j, n, nthreads);
+}
+
+uint64_t orc_fill_polar(int kind, uint64_t seed, uint32_t s, uint64_t first, uint64_t n,
+                        uint32_t dmax, double *out, uint8_t *cls, int nthreads) {
+  orc_job j = {0, 2, kind, seed, s, first, 0, 0, dmax, 0.0, out, 0, cls, 0};
+  return run_split(j, n, nthreads);
+}
+
+uint64_t orc_mutate(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t first,
+                    uint64_t n, uint32_t dmax, double sigma, double *x, uint8_t *cls,
+                    int nthreads) {
+  orc_job j = {T, 3, kind, seed, s, first, 0, 0, dmax, sigma, x, 0, cls, 0};
+  return run_split(j, n, nthreads);
+}
+
+/* Raw words W(seed, s, first + k, d) for k < n. */
+void orc_words(int kind, uint64_t seed, uint32_t s, uint32_t d, uint64_t first, uint64_t n,
+               uint64_t *out) {
+  for (uint64_t k = 0; k < n; ++k) out[k] = orc_word(kind, seed, s, first + k, d);
+}
