@@ -1,0 +1,58 @@
+"""Builds libzg.so (HIP for gfx950 + host C++) in-tree with hipcc."""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libzg.so")
+SOURCES = ["zg_kernels.hip", "zg_table.cpp", "zg_api.cpp", "zg_batch.cpp", "zg_tune.cpp",
+           "zg_server.cpp"]
+ARCH = os.environ.get("ZG_OFFLOAD_ARCH", "gfx950")
+
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "-Wall",
+    # bit-exact fast path and wedge arithmetic: no FMA contraction
+    "-ffp-contract=off",
+    # no packed FP32 instructions in device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def build(verbose=False):
+    """Compiles every source and links libzg.so; always rebuilds."""
+    objs = []
+    obj_dir = os.path.join(HERE, "_build")
+    os.makedirs(obj_dir, exist_ok=True)
+    procs = []
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        if not os.path.exists(path):
+            continue
+        obj = os.path.join(obj_dir, src + ".o")
+        cmd = ["hipcc", f"--offload-arch={ARCH}", *FLAGS, "-c", path, "-o", obj]
+        if src.endswith(".cpp"):
+            cmd = ["hipcc", *FLAGS, "-x", "hip", f"--offload-arch={ARCH}", "-c", path, "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        objs.append(obj)
+    failed = False
+    for src, p in procs:
+        out, _ = p.communicate()
+        text = out.decode(errors="replace")
+        text = "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+        if verbose or p.returncode:
+            if text.strip():
+                print(f"[{src}]\n{text}", file=sys.stderr)
+        if p.returncode:
+            failed = True
+    if failed:
+        raise RuntimeError("libzg build failed")
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

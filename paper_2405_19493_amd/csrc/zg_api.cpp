@@ -1,0 +1,441 @@
+// Host side of libzg: context, argument checking, launches, device counters,
+// the graph-captured batch path and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "zg_ctx.h"
+
+using namespace zg;
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+const zg_tune DEFAULT_TUNE[ZG_TUNE_CLASSES] = {
+    {2048, 8, 2, 0},    // FILL_F64
+    {4096, 8, 2, 0},    // FILL_F32
+    {2048, 8, 2, 0},    // POLAR
+    {2048, 8, 2, 0},    // MUTATE
+    {2048, 8, 4, 0},    // BATCH (k_batch is bounded to 512 threads)
+};
+
+uint32_t chunk_of(uint32_t op) { return op == OP_ZIG32 ? 256u : 128u; }
+
+int tune_class(uint32_t op) {
+  switch (op) {
+    case OP_ZIG64: return ZG_TUNE_FILL_F64;
+    case OP_ZIG32: return ZG_TUNE_FILL_F32;
+    case OP_POLAR: return ZG_TUNE_POLAR;
+    default: return ZG_TUNE_MUTATE;
+  }
+}
+
+}  // namespace
+
+namespace zg {
+
+zg_status hip_fail(const zg_ctx *ctx, hipError_t e, const char *what) {
+  if (ctx) {
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    ctx->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return ZG_EHIP;
+}
+
+uint64_t window_of(uint32_t kind) { return kind == ZG_JAVA_LCG48 ? ZG_LCG_WINDOW : ZG_SM64_WINDOW; }
+uint32_t max_streams_of(uint32_t kind) {
+  return kind == ZG_JAVA_LCG48 ? ZG_LCG_MAX_STREAMS : ZG_SM64_MAX_STREAMS;
+}
+
+// Shared validation of a generation request; fills *op.
+zg_status check_gen(const void *out, uint64_t n_total, zg_dtype dtype, zg_method method,
+                    zg_kind kind, uint32_t stream0, uint32_t n_streams, uint64_t first,
+                    uint64_t n_per, uint32_t *op) {
+  if (kind != ZG_SPLITMIX64 && kind != ZG_JAVA_LCG48) return ZG_EINVAL;
+  if (dtype != ZG_F64 && dtype != ZG_F32) return ZG_EINVAL;
+  if (method != ZG_ZIGGURAT && method != ZG_POLAR) return ZG_EINVAL;
+  if (method == ZG_POLAR && dtype != ZG_F64) return ZG_EINVAL;
+  if (n_total > 0 && !out) return ZG_EINVAL;
+  if (n_total >= (1ull << 40)) return ZG_EINVAL;   // queue entries hold 40-bit element indices
+  size_t esz = dtype == ZG_F64 ? 8 : 4;
+  if (((uintptr_t)out) % esz) return ZG_EINVAL;
+  if (n_streams == 0 || (uint64_t)stream0 + n_streams > max_streams_of(kind)) return ZG_EINVAL;
+  if (first + n_per < first || first + n_per > window_of(kind)) return ZG_ERANGE;
+  *op = method == ZG_POLAR ? OP_POLAR : (dtype == ZG_F32 ? OP_ZIG32 : OP_ZIG64);
+  return ZG_OK;
+}
+
+uint32_t head_of(const void *out, uint32_t op, uint64_t n) {
+  uintptr_t a = (uintptr_t)out;
+  uint64_t h;
+  if (op == OP_ZIG32)
+    h = (4 - ((a >> 2) & 3)) & 3;
+  else
+    h = (a >> 3) & 1;
+  return (uint32_t)std::min<uint64_t>(h, n);
+}
+
+zg_status launch_job(zg_ctx *ctx, const Job &J, hipStream_t stream) {
+  if (J.n_total == 0) return ZG_OK;
+  const zg_tune &t = ctx->tune[tune_class(J.op)];
+  uint32_t head = head_of(J.out, J.op, J.n_total);
+  hipError_t e = launch_fill(J, ctx->d_tables, ctx->dmax, ctx->d_flags, t.tile, t.waves_per_block,
+                             head, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "launch_fill");
+  return ZG_OK;
+}
+
+}  // namespace zg
+
+// =================================================================== ABI
+
+extern "C" {
+
+const char *zg_strerror(zg_status st) {
+  switch (st) {
+    case ZG_OK: return "ok";
+    case ZG_EINVAL: return "invalid argument";
+    case ZG_ERANGE: return "index range beyond the stream window";
+    case ZG_ENOMEM: return "out of memory";
+    case ZG_EHIP: return "HIP runtime error";
+    case ZG_EBUSY: return "busy / admission refused";
+    case ZG_ENOENT: return "unknown handle or ticket";
+    case ZG_ESTATE: return "object in the wrong state";
+    default: return "unknown status";
+  }
+}
+
+const char *zg_last_error(const zg_ctx *ctx) {
+  if (!ctx) return "";
+  std::lock_guard<std::mutex> lk(ctx->err_mu);
+  return ctx->last_error.c_str();
+}
+
+zg_status zg_create(int hip_device, zg_ctx **out) {
+  if (!out) return ZG_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+    return ZG_EINVAL;
+  DeviceGuard g(hip_device);
+  zg_ctx *ctx = new (std::nothrow) zg_ctx();
+  if (!ctx) return ZG_ENOMEM;
+  ctx->device = hip_device;
+  zg_status st = build_table(&ctx->table);
+  if (st != ZG_OK) {
+    delete ctx;
+    return st;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+    ctx->num_cus = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+  }
+  // device tables
+  DevTables *h = new (std::nothrow) DevTables();
+  if (!h) {
+    delete ctx;
+    return ZG_ENOMEM;
+  }
+  std::memset(h, 0, sizeof(*h));
+  for (int i = 0; i < ZG_LAYERS; ++i) {
+    h->fast64[i] = {ctx->table.k53[i], ctx->table.w53[i]};
+    h->fast32[i] = {ctx->table.k24[i], ctx->table.w24[i]};
+    h->y[i] = ctx->table.y[i];
+    h->dy[i] = ctx->table.dy[i];
+    h->w53[i] = ctx->table.w53[i];
+    h->w24d[i] = ctx->table.w24d[i];
+  }
+  h->r = ctx->table.r;
+  build_lcg_tables(&h->lcg);
+  hipError_t e = hipMalloc(&ctx->d_tables, sizeof(DevTables));
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_tables, h, sizeof(DevTables), hipMemcpyHostToDevice);
+  delete h;
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_flags, 64);
+  if (e == hipSuccess) e = hipMemset(ctx->d_flags, 0, 64);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_counters, sizeof(uint64_t) * ZG_MAX_HANDLES);
+  if (e == hipSuccess) e = hipMemset(ctx->d_counters, 0, sizeof(uint64_t) * ZG_MAX_HANDLES);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    zg_destroy(ctx);
+    return ZG_EHIP;
+  }
+  for (int c = 0; c < ZG_TUNE_CLASSES; ++c) ctx->tune[c] = DEFAULT_TUNE[c];
+  ctx->handles.resize(ZG_MAX_HANDLES);
+  *out = ctx;
+  return ZG_OK;
+}
+
+zg_status zg_destroy(zg_ctx *ctx) {
+  if (!ctx) return ZG_OK;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto &s : ctx->slots) s.release();
+  if (ctx->d_tables) (void)hipFree(ctx->d_tables);
+  if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+  if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+  delete ctx;
+  return ZG_OK;
+}
+
+zg_status zg_build_table(zg_table_view *out);
+
+zg_status zg_table(const zg_ctx *ctx, zg_table_view *out) {
+  if (!ctx || !out) return ZG_EINVAL;
+  *out = ctx->table;
+  return ZG_OK;
+}
+
+zg_status zg_fill_streams(zg_ctx *ctx, void *d_out, uint64_t n_per_stream, uint32_t n_streams,
+                          zg_dtype dtype, zg_method method, zg_kind kind, uint64_t seed,
+                          uint32_t stream0, uint64_t first_index, void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  if (n_streams && n_per_stream > UINT64_MAX / n_streams) return ZG_EINVAL;
+  uint64_t n_total = n_per_stream * n_streams;
+  uint32_t op;
+  zg_status st = check_gen(d_out, n_total, dtype, method, kind, stream0, n_streams, first_index,
+                           n_per_stream, &op);
+  if (st != ZG_OK || n_total == 0) return st;
+  Job J{};
+  J.out = d_out;
+  J.n_per = n_per_stream;
+  J.n_total = n_total;
+  J.first = first_index;
+  J.seed = seed;
+  J.sigma = 0.0;
+  J.s0 = stream0;
+  J.n_streams = n_streams;
+  J.kind = kind;
+  J.op = op;
+  DeviceGuard g(ctx->device);
+  return launch_job(ctx, J, (hipStream_t)hip_stream);
+}
+
+zg_status zg_fill(zg_ctx *ctx, void *d_out, uint64_t n, zg_dtype dtype, zg_method method,
+                  zg_kind kind, uint64_t seed, uint32_t stream, uint64_t first_index,
+                  void *hip_stream) {
+  return zg_fill_streams(ctx, d_out, n, 1, dtype, method, kind, seed, stream, first_index,
+                         hip_stream);
+}
+
+zg_status zg_mutate(zg_ctx *ctx, double *d_x, uint64_t n, double sigma, zg_kind kind,
+                    uint64_t seed, uint32_t stream, uint64_t first_index, void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  uint32_t op;
+  zg_status st = check_gen(d_x, n, ZG_F64, ZG_ZIGGURAT, kind, stream, 1, first_index, n, &op);
+  if (st != ZG_OK || n == 0) return st;
+  Job J{};
+  J.out = d_x;
+  J.n_per = n;
+  J.n_total = n;
+  J.first = first_index;
+  J.seed = seed;
+  J.sigma = sigma;
+  J.s0 = stream;
+  J.n_streams = 1;
+  J.kind = kind;
+  J.op = OP_MUTATE;
+  DeviceGuard g(ctx->device);
+  return launch_job(ctx, J, (hipStream_t)hip_stream);
+}
+
+zg_status zg_uniform_words(zg_ctx *ctx, uint64_t *d_out, uint64_t n, zg_kind kind, uint64_t seed,
+                           uint32_t stream, uint32_t draw, uint64_t first_index,
+                           void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  if (kind != ZG_SPLITMIX64 && kind != ZG_JAVA_LCG48) return ZG_EINVAL;
+  if (n == 0) return ZG_OK;
+  if (!d_out || ((uintptr_t)d_out) % 8) return ZG_EINVAL;
+  if (stream >= max_streams_of(kind) || draw >= ZG_MAX_DRAWS) return ZG_EINVAL;
+  if (first_index + n < first_index || first_index + n > window_of(kind)) return ZG_ERANGE;
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_words(d_out, n, ctx->d_tables, kind, seed, stream, draw, first_index,
+                              (hipStream_t)hip_stream);
+  return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "launch_words");
+}
+
+zg_status zg_decide_words(zg_ctx *ctx, const uint64_t *d_words, uint64_t n, uint8_t *d_class,
+                          double *d_x, void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  if (n == 0) return ZG_OK;
+  if (!d_words || !d_class || !d_x || ((uintptr_t)d_words) % 8 || ((uintptr_t)d_x) % 8)
+    return ZG_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_decide(d_words, n, ctx->d_tables, d_class, d_x, (hipStream_t)hip_stream);
+  return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "launch_decide");
+}
+
+zg_status zg_error_flags(zg_ctx *ctx, uint32_t *flags, int clear) {
+  if (!ctx || !flags) return ZG_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(flags, ctx->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && clear) e = hipMemset(ctx->d_flags, 0, sizeof(uint32_t));
+  if (e == hipSuccess && clear) e = hipDeviceSynchronize();
+  return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "zg_error_flags");
+}
+
+zg_status zg_set_test_knob(zg_ctx *ctx, int knob, int64_t value) {
+  if (!ctx) return ZG_EINVAL;
+  if (knob == ZG_KNOB_DMAX) {
+    if (value < 1 || value > (int64_t)ZG_MAX_DRAWS) return ZG_EINVAL;
+    ctx->dmax = (uint32_t)value;
+    return ZG_OK;
+  }
+  return ZG_EINVAL;
+}
+
+// ------------------------------------------------------------- handles
+
+zg_status zg_stream_open(zg_ctx *ctx, uint64_t seed, uint32_t stream, zg_kind kind,
+                         zg_handle *out) {
+  if (!ctx || !out) return ZG_EINVAL;
+  if (kind != ZG_SPLITMIX64 && kind != ZG_JAVA_LCG48) return ZG_EINVAL;
+  if (stream >= max_streams_of(kind)) return ZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (uint32_t h = 0; h < ZG_MAX_HANDLES; ++h) {
+    uint32_t k = (ctx->next_handle + h) % ZG_MAX_HANDLES;
+    if (!ctx->handles[k].open) {
+      DeviceGuard g(ctx->device);
+      uint64_t zero = 0;
+      hipError_t e = hipMemcpy(ctx->d_counters + k, &zero, 8, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(ctx, e, "zg_stream_open");
+      ctx->handles[k] = {seed, stream, (uint32_t)kind, true};
+      ctx->next_handle = k + 1;
+      *out = k;
+      return ZG_OK;
+    }
+  }
+  return ZG_EBUSY;
+}
+
+zg_status zg_stream_close(zg_ctx *ctx, zg_handle h) {
+  if (!ctx) return ZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (h >= ZG_MAX_HANDLES || !ctx->handles[h].open) return ZG_ENOENT;
+  ctx->handles[h].open = false;
+  return ZG_OK;
+}
+
+zg_status zg_stream_get_counter(zg_ctx *ctx, zg_handle h, uint64_t *counter) {
+  if (!ctx || !counter) return ZG_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (h >= ZG_MAX_HANDLES || !ctx->handles[h].open) return ZG_ENOENT;
+  }
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(counter, ctx->d_counters + h, 8, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "zg_stream_get_counter");
+}
+
+zg_status zg_stream_set_counter(zg_ctx *ctx, zg_handle h, uint64_t counter) {
+  if (!ctx) return ZG_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (h >= ZG_MAX_HANDLES || !ctx->handles[h].open) return ZG_ENOENT;
+    if (counter > window_of(ctx->handles[h].kind)) return ZG_ERANGE;
+  }
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_counters + h, &counter, 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "zg_stream_set_counter");
+}
+
+zg_status zg_stream_fill(zg_ctx *ctx, zg_handle h, void *d_out, uint64_t n, zg_dtype dtype,
+                         zg_method method, void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  zg_request r{};
+  r.out = d_out;
+  r.n = n;
+  r.handle = (int32_t)h;
+  r.dtype = (uint8_t)dtype;
+  r.method = (uint8_t)method;
+  r.op = ZG_OP_FILL;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (h >= ZG_MAX_HANDLES || !ctx->handles[h].open) return ZG_ENOENT;
+    r.kind = (uint8_t)ctx->handles[h].kind;
+  }
+  return zg_batch(ctx, &r, 1, nullptr, hip_stream);
+}
+
+// ---------------------------------------------------------------- batch
+
+zg_status zg_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, uint64_t *first_out,
+                   void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  if (nreq == 0) return ZG_OK;
+  if (!reqs || nreq > ZG_MAX_BATCH) return ZG_EINVAL;
+  DeviceGuard g(ctx->device);
+  BatchPlan plan;
+  zg_status st = plan_batch(ctx, reqs, nreq, nullptr, 0, &plan);
+  if (st != ZG_OK) return st;
+  if (plan.reqs.empty()) {
+    if (first_out)
+      for (uint32_t i = 0; i < nreq; ++i) first_out[i] = reqs[i].first_index;
+    return ZG_OK;
+  }
+  BatchSlot *slot = nullptr;
+  st = acquire_slot(ctx, &slot);
+  if (st != ZG_OK) return st;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  st = slot->launch(ctx, plan, stream, /*full=*/true, nullptr);
+  if (st == ZG_OK && first_out) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) st = hip_fail(ctx, e, "zg_batch sync");
+    if (st == ZG_OK) {
+      std::vector<DevRequest> back(plan.reqs.size());
+      e = hipMemcpy(back.data(), slot->d_reqs(), back.size() * sizeof(DevRequest),
+                    hipMemcpyDeviceToHost);
+      if (e != hipSuccess) st = hip_fail(ctx, e, "zg_batch readback");
+      for (uint32_t i = 0; i < nreq; ++i) first_out[i] = reqs[i].first_index;
+      for (size_t k = 0; k < plan.reqs.size() && st == ZG_OK; ++k)
+        first_out[plan.index[k]] = back[k].job.first;
+    }
+  }
+  release_slot(ctx, slot);
+  return st;
+}
+
+// ---------------------------------------------------------------- tuning
+
+zg_status zg_get_tune(const zg_ctx *ctx, int cls, zg_tune *out) {
+  if (!ctx || !out || cls < 0 || cls >= ZG_TUNE_CLASSES) return ZG_EINVAL;
+  *out = ctx->tune[cls];
+  return ZG_OK;
+}
+
+zg_status zg_set_tune(zg_ctx *ctx, int cls, const zg_tune *in) {
+  if (!ctx || !in || cls < 0 || cls >= ZG_TUNE_CLASSES) return ZG_EINVAL;
+  uint32_t ch = cls == ZG_TUNE_FILL_F32 ? 256u : 128u;
+  if (in->tile == 0 || in->tile % ch || in->tile > (1u << 20)) return ZG_EINVAL;
+  if (in->waves_per_block < 1 || in->waves_per_block > 16) return ZG_EINVAL;
+  if (in->batch_blocks_per_cu < 1 || in->batch_blocks_per_cu > 8) return ZG_EINVAL;
+  if (cls == ZG_TUNE_BATCH && (in->tile % 256 || in->waves_per_block > 8)) return ZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->tune[cls] = *in;
+  if (cls == ZG_TUNE_BATCH)
+    for (auto &s : ctx->slots) s.invalidate_graphs();
+  return ZG_OK;
+}
+
+}  // extern "C"

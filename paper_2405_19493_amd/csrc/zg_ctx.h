@@ -1,0 +1,88 @@
+// The context object behind the C ABI, and the batch machinery shared by
+// zg_batch, zg_stream_fill and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "zg_internal.h"
+
+namespace zg {
+
+struct HandleInfo {
+  uint64_t seed;
+  uint32_t stream;
+  uint32_t kind;
+  bool open;
+};
+
+// A validated batch ready for upload: only requests with n > 0, in order.
+struct BatchPlan {
+  std::vector<DevRequest> reqs;
+  std::vector<uint32_t> index;   // position of each planned request in the caller's array
+  uint64_t total_tiles = 0;
+  uint64_t total_elems = 0;
+};
+
+struct BatchSlot {
+  void *h_buf = nullptr;   // pinned staging: BatchHeader + DevRequest[cap]
+  void *d_buf = nullptr;
+  size_t cap = 0;
+  hipGraph_t g_full = nullptr, g_prep = nullptr, g_run = nullptr;
+  hipGraphExec_t x_full = nullptr, x_prep = nullptr, x_run = nullptr;
+  hipGraphNode_t cpy_full = nullptr, cpy_prep = nullptr;
+  hipEvent_t done = nullptr;   // recorded after the last use of the staging buffer
+  bool busy = false;
+  bool recorded = false;
+
+  DevRequest *d_reqs() const { return (DevRequest *)((char *)d_buf + sizeof(BatchHeader)); }
+  zg_status ensure(struct ::zg_ctx *ctx, size_t nreq);
+  zg_status build_graphs(struct ::zg_ctx *ctx);
+  void invalidate_graphs();
+  void release();
+  // Uploads the plan and launches.  full: one graph {copy, reserve, batch} on
+  // `stream`.  Otherwise the graph {copy, reserve} goes on `stream`, an event
+  // is recorded in *prep_done, and the batch kernel graph goes on run_stream
+  // after waiting for that event.
+  zg_status launch(struct ::zg_ctx *ctx, const BatchPlan &plan, hipStream_t stream, bool full,
+                   hipStream_t run_stream, hipEvent_t prep_done = nullptr);
+};
+
+zg_status hip_fail(const struct ::zg_ctx *ctx, hipError_t e, const char *what);
+uint64_t window_of(uint32_t kind);
+uint32_t max_streams_of(uint32_t kind);
+zg_status check_gen(const void *out, uint64_t n_total, zg_dtype dtype, zg_method method,
+                    zg_kind kind, uint32_t stream0, uint32_t n_streams, uint64_t first,
+                    uint64_t n_per, uint32_t *op);
+uint32_t head_of(const void *out, uint32_t op, uint64_t n);
+zg_status launch_job(struct ::zg_ctx *ctx, const Job &J, hipStream_t stream);
+
+// done_flags (host-visible, optional): completion word of request i is
+// done_flags[i], written with done_value when its last tile finishes.
+zg_status plan_batch(struct ::zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
+                     uint32_t *const *done_flags, uint32_t done_value, BatchPlan *plan);
+zg_status acquire_slot(struct ::zg_ctx *ctx, BatchSlot **out);
+void release_slot(struct ::zg_ctx *ctx, BatchSlot *slot);
+
+}  // namespace zg
+
+struct zg_ctx {
+  int device = 0;
+  int num_cus = 256;
+  std::string arch;
+  zg_table_view table;
+  zg::DevTables *d_tables = nullptr;
+  uint32_t *d_flags = nullptr;
+  uint64_t *d_counters = nullptr;
+  uint32_t dmax = ZG_MAX_DRAWS;
+  zg_tune tune[ZG_TUNE_CLASSES];
+  std::vector<zg::HandleInfo> handles;
+  uint32_t next_handle = 0;
+  std::vector<zg::BatchSlot> slots;   // reserved up front; never reallocated
+  std::mutex mu;                      // handles, slots, tune
+  mutable std::mutex err_mu;
+  mutable std::string last_error;
+};

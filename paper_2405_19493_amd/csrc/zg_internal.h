@@ -1,0 +1,111 @@
+// Internal declarations shared by the host and device sources of libzg.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/zg.h"
+
+namespace zg {
+
+constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t LCG_A = 0x5DEECE66Dull;
+constexpr uint64_t LCG_C = 0xBull;
+constexpr uint64_t LCG_M48 = (1ull << 48) - 1;
+constexpr int LCG_JUMP_BYTES = 6;
+
+// S -> (A S + C) mod 2^48: `k` LCG steps.
+struct Affine {
+  uint64_t A, C;
+};
+
+struct LcgTables {
+  Affine jump[LCG_JUMP_BYTES][256];   // x * 256^b steps
+  Affine window[256];                 // 2 d ZG_LCG_WINDOW steps
+};
+
+// Fast-path table entries, packed so one LDS read serves one lane.
+struct Fast64 {
+  uint64_t k;   // k53
+  double w;     // w53
+};
+struct Fast32 {
+  uint32_t k;   // k24
+  float w;      // w24
+};
+
+// Everything the kernels read, in one device allocation per context.
+struct DevTables {
+  Fast64 fast64[ZG_LAYERS];
+  Fast32 fast32[ZG_LAYERS];
+  double y[ZG_LAYERS];
+  double dy[ZG_LAYERS];
+  double w53[ZG_LAYERS];
+  double w24d[ZG_LAYERS];
+  double r;
+  double pad[7];
+  LcgTables lcg;
+};
+
+// Operation selector shared by the plain and batch kernels.
+enum Op : uint32_t { OP_ZIG64 = 0, OP_ZIG32 = 1, OP_POLAR = 2, OP_MUTATE = 3 };
+
+// One generation job over elements [0, n_streams * n_per) of an output:
+// element e is variate first + (e mod n_per) of stream s0 + e / n_per.
+struct Job {
+  void *out;
+  uint64_t n_per;
+  uint64_t n_total;
+  uint64_t first;
+  uint64_t seed;
+  double sigma;
+  uint32_t s0;
+  uint32_t n_streams;
+  uint32_t kind;
+  uint32_t op;
+};
+
+// A batch request as the device sees it (host fills all but `first`,
+// which the reserve kernel resolves from the counters when handle >= 0).
+struct DevRequest {
+  Job job;
+  uint64_t off;          // counter offset of this request among earlier
+                         // requests of the same handle in the batch
+  uint64_t tile0;        // first global tile index of this request
+  int32_t handle;
+  uint32_t last_of_handle;   // 1: advance the counter by off + n after the batch
+  uint64_t limit;        // index window of the kind (first + n must stay <= limit)
+  uint32_t *done_flag;   // host-visible completion word (may be null)
+  uint32_t done_value;
+  uint32_t tiles;        // number of tiles of this request
+  uint32_t status;       // 0 ok, ZG_FLAG_RANGE when skipped
+  uint32_t remaining;    // tiles not yet finished (counted down on the device)
+  uint32_t tile;         // elements per tile
+  uint32_t head;         // elements before the first 16-byte aligned one
+};
+
+// Batch header, uploaded with the requests.
+struct BatchHeader {
+  uint32_t nreq;
+  uint32_t dmax;
+  uint64_t total_tiles;
+  uint64_t pad[6];
+};
+
+// Host entry points of the device code (zg_kernels.hip).
+hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
+                       uint32_t tile, uint32_t waves, uint32_t head, hipStream_t stream);
+hipError_t launch_words(uint64_t *out, uint64_t n, const DevTables *T, uint32_t kind,
+                        uint64_t seed, uint32_t s, uint32_t d, uint64_t first, hipStream_t stream);
+hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, uint8_t *cls,
+                         double *x, hipStream_t stream);
+const void *kernel_reserve();
+const void *kernel_batch();
+size_t batch_lds_bytes(uint32_t waves);
+
+zg_status build_table(zg_table_view *t);
+void build_lcg_tables(LcgTables *L);
+Affine lcg_power(uint64_t k);
+
+}  // namespace zg

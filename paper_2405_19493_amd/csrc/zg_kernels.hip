@@ -1,0 +1,789 @@
+// Device code of libzg for gfx950 (CDNA4, wave64).
+//
+// Hot path (Section 1 / Section 2 "Ziggurat": the original 128-layer
+// ziggurat of Marsaglia-Tsang and Leong, as in GSL):
+//   keyed uniform word -> decode (layer, sign, j) -> fast accept j < k[i]
+//   with x = j w[i] (one multiply and one compare per lane) -> coalesced
+//   128-bit stores.  Lanes that fail the fast test are compacted with a wave
+//   ballot and a lane prefix count into a per-wave LDS queue; the queue is
+//   drained 64 entries at a time, each lane running the wedge / tail / retry
+//   loop for one queued variate, so the rare slow path does not diverge the
+//   fast one.  Every variate is a pure function of its index, so the launch
+//   shape, the queue order and the batch layout never change the bits.
+//
+// Build with -ffp-contract=off: the fast-path product and the wedge
+// y = y[i-1] + U dy[i] must be rounded exactly as written.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "zg_internal.h"
+
+namespace zg {
+
+#define DEV __device__ __forceinline__
+
+constexpr uint64_t MASK53 = (1ull << 53) - 1;
+constexpr int QCAP = 320;              // queue entries per wave (>= 63 + largest step)
+constexpr uint64_t E_MASK = (1ull << 40) - 1;
+
+// ------------------------------------------------------------ uniform words
+
+DEV uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+DEV uint64_t sm64_word(uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  return mix64(seed + GAMMA * (1ull + ((uint64_t)s << 48) + ((uint64_t)d << 40) + v));
+}
+
+DEV uint64_t aff(Affine f, uint64_t S) { return (f.A * S + f.C) & LCG_M48; }
+
+DEV Affine aff_cat(Affine first, Affine second) {
+  return {(second.A * first.A) & LCG_M48, (second.A * first.C + second.C) & LCG_M48};
+}
+
+DEV uint64_t lcg_state0(uint64_t seed) { return (seed ^ LCG_A) & LCG_M48; }
+
+// Advance a state by k < 2^48 steps with the byte tables (the maps commute).
+DEV uint64_t lcg_jump(const LcgTables *L, uint64_t S, uint64_t k) {
+#pragma unroll
+  for (int b = 0; b < LCG_JUMP_BYTES; ++b) {
+    uint32_t x = (uint32_t)(k >> (8 * b)) & 255u;
+    if (x) S = aff(L->jump[b][x], S);
+  }
+  return S;
+}
+
+DEV uint64_t lcg_index(uint32_t s, uint64_t v, uint32_t d) {
+  return (uint64_t)s * ZG_LCG_STREAM_SPACING + (uint64_t)d * ZG_LCG_WINDOW + v;
+}
+
+// The word of the nextDouble whose first LCG state (step 2m+1) is S1.
+DEV uint64_t lcg_word_from(uint64_t S1) {
+  uint64_t S2 = (LCG_A * S1 + LCG_C) & LCG_M48;
+  return (((S1 >> 22) << 27) + (S2 >> 21)) << 11;
+}
+
+DEV double u53(uint64_t W) { return (double)(W >> 11) * 0x1p-53; }
+DEV double u53p(uint64_t W) { return (double)((W >> 11) + 1) * 0x1p-53; }
+
+DEV double nan64() { return __longlong_as_double(0x7FF8000000000000ll); }
+DEV float nan32() { return __int_as_float(0x7FC00000); }
+
+DEV double flip(double x, uint64_t neg) {
+  return __longlong_as_double(__double_as_longlong(x) ^ (long long)(neg << 63));
+}
+
+// ------------------------------------------------------- slow path (FP64)
+
+// Word of draw d for variate v of stream s, specialised on the kind.
+template <int KIND>
+DEV uint64_t wordk(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  if (KIND == ZG_JAVA_LCG48)
+    return lcg_word_from(lcg_jump(&T->lcg, lcg_state0(seed), 2 * lcg_index(s, v, d) + 1));
+  return sm64_word(seed, s, v, d);
+}
+
+struct Step {
+  int status;        // 1 accepted, 0 rejected, -1 draw budget exhausted
+  double x;
+  uint32_t next_d;
+};
+
+// Wedge (i >= 1) or tail (i == 0) test of the attempt at draw d whose first
+// word gave candidate x in layer i.
+template <int KIND>
+DEV Step slow_step(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, uint32_t d,
+                   uint32_t dmax, uint32_t i, double x) {
+  if (i == 0) {
+    if (d + 2 >= dmax) return {-1, 0.0, d};
+    double u1 = u53p(wordk<KIND>(T, seed, s, v, d + 1));
+    double u2 = u53(wordk<KIND>(T, seed, s, v, d + 2));
+    double r = T->r;
+    double a = -log(u1) / r;
+    double xt = r + a;
+    return {u2 < exp(-0.5 * (a * a)) ? 1 : 0, xt, d + 3};
+  }
+  if (d + 1 >= dmax) return {-1, 0.0, d};
+  double u = u53(wordk<KIND>(T, seed, s, v, d + 1));
+  double y = T->y[i - 1] + u * T->dy[i];
+  return {y < exp(-0.5 * (x * x)) ? 1 : 0, x, d + 2};
+}
+
+// One full FP64 attempt at draw d (signed result on acceptance).
+template <int KIND>
+DEV Step attempt64(const DevTables *T, const Fast64 *fast, uint64_t seed, uint32_t s, uint64_t v,
+                   uint32_t d, uint32_t dmax) {
+  if (d >= dmax) return {-1, 0.0, d};
+  uint64_t W = wordk<KIND>(T, seed, s, v, d);
+  uint32_t i = (uint32_t)(W >> 57);
+  Fast64 f = fast[i];
+  uint64_t j = (W >> 3) & MASK53;
+  double x = (double)j * f.w;
+  Step st;
+  if (j < f.k)
+    st = {1, x, d};
+  else
+    st = slow_step<KIND>(T, seed, s, v, d, dmax, i, x);
+  if (st.status == 1) st.x = flip(st.x, (W >> 56) & 1);
+  return st;
+}
+
+struct Step32 {
+  int status;
+  float x;
+  uint32_t next_d;
+};
+
+// The 32-bit attempt word of FP32 mode.
+template <int KIND>
+DEV uint32_t word32(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  if (d == 0 && KIND == ZG_SPLITMIX64) {
+    uint64_t W = sm64_word(seed, s, v >> 1, 0);
+    return (v & 1) ? (uint32_t)W : (uint32_t)(W >> 32);
+  }
+  return (uint32_t)(wordk<KIND>(T, seed, s, v, d) >> 32);
+}
+
+template <int KIND>
+DEV Step32 attempt32(const DevTables *T, const Fast32 *fast, uint64_t seed, uint32_t s, uint64_t v,
+                     uint32_t d, uint32_t dmax) {
+  if (d >= dmax) return {-1, 0.f, d};
+  uint32_t u = word32<KIND>(T, seed, s, v, d);
+  uint32_t i = u >> 25;
+  uint32_t neg = (u >> 24) & 1;
+  uint32_t j = u & 0xFFFFFFu;
+  Fast32 f = fast[i];
+  if (j < f.k) {
+    float xf = (float)j * f.w;
+    return {1, neg ? -xf : xf, d};
+  }
+  double x = (double)j * T->w24d[i];
+  Step st = slow_step<KIND>(T, seed, s, v, d, dmax, i, x);
+  float xf = (float)(neg ? -st.x : st.x);
+  return {st.status, xf, st.next_d};
+}
+
+struct PolarStep {
+  int status;
+  double z1, z2;
+  uint32_t next_d;
+};
+
+// Polar attempt from the words of draws d and d+1 (Knuth; Random.nextGaussian).
+DEV PolarStep polar_from_words(uint64_t W1, uint64_t W2, uint32_t d) {
+  double v1 = 2.0 * u53(W1) - 1.0;
+  double v2 = 2.0 * u53(W2) - 1.0;
+  double ss = v1 * v1 + v2 * v2;
+  if (ss >= 1.0 || ss == 0.0) return {0, 0.0, 0.0, d + 2};
+  double m = sqrt(-2.0 * log(ss) / ss);
+  return {1, v1 * m, v2 * m, d};
+}
+
+template <int KIND>
+DEV PolarStep polar_attempt(const DevTables *T, uint64_t seed, uint32_t s, uint64_t p, uint32_t d,
+                            uint32_t dmax) {
+  if (d + 1 >= dmax) return {-1, 0.0, 0.0, d};
+  return polar_from_words(wordk<KIND>(T, seed, s, p, d), wordk<KIND>(T, seed, s, p, d + 1), d);
+}
+
+// --------------------------------------------------------- wave utilities
+
+DEV uint32_t lane_id() { return __lane_id(); }
+
+DEV uint32_t prefix_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+DEV uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+DEV uint64_t uni64(uint64_t x) {
+  return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+
+// Queue entry: variate index v (40 bits), stream s (16 bits), draw d (8 bits).
+// The element index is (s - s0) n_per + (v - first): no division on drain.
+// Polar entries hold an even draw; its low bit marks "both elements of the pair".
+DEV uint64_t qentry(uint32_t s, uint64_t v, uint32_t d) {
+  return v | ((uint64_t)s << 40) | ((uint64_t)d << 56);
+}
+
+// Appends up to two entries per lane (a, then b).  Wave-uniform control flow
+// only: the queue count qn is the same in every lane.
+DEV void qpush2(uint64_t *q, uint32_t &qn, bool pa, uint64_t ea, bool pb, uint64_t eb) {
+  const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+  if ((ma | mb) != 0) {
+    const uint32_t base = qn + prefix_below(ma) + prefix_below(mb);
+    if (pa) q[base] = ea;
+    if (pb) q[base + (pa ? 1u : 0u)] = eb;
+    qn = uni(qn + (uint32_t)__popcll(ma) + (uint32_t)__popcll(mb));
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Element e of a job -> (stream, variate index).  Divides: used only for the
+// alignment head and for chunks that straddle a stream boundary.
+DEV void split(const Job &J, uint64_t e, uint32_t &s, uint64_t &v) {
+  if (J.n_streams == 1) {
+    s = J.s0;
+    v = J.first + e;
+  } else {
+    uint64_t k = e / J.n_per;
+    s = J.s0 + (uint32_t)k;
+    v = J.first + (e - k * J.n_per);
+  }
+}
+
+struct Ctx {
+  const DevTables *T;
+  const Fast64 *f64;   // LDS
+  const Fast32 *f32;   // LDS
+  uint32_t dmax;
+  uint32_t *flags;
+};
+
+DEV void raise_flag(uint32_t *flags, uint32_t bit) { atomicOr(flags, bit); }
+
+// Sign from bit 24 of the word's high dword, applied to the double's high dword.
+// The empty asm keeps the compiler from re-deriving that bit from the last
+// multiply of the hash (it would spend three extra multiplies on it).
+DEV double flip_hi(double x, uint32_t whi) {
+  asm volatile("" : "+v"(whi));
+  return __hiloint2double(__double2hiint(x) ^ (int)((whi << 7) & 0x80000000u), __double2loint(x));
+}
+
+// ------------------------------------------------------------ queue drain
+
+// Processes queued variates 64 at a time until at most `keep` remain; each
+// lane loops over attempts of its own variate until acceptance or the budget
+// (the loop always ends: every rejection advances the draw index by >= 2).
+template <int OP, int KIND>
+DEV void drain(const Job &J, const Ctx &C, uint64_t *q, uint32_t &qn, uint32_t keep) {
+  const uint32_t lane = lane_id();
+  if (qn > keep) __threadfence_block();   // placeholders are written before any patch
+  while (qn > keep) {
+    const uint32_t m = qn < 64 ? qn : 64;
+    const bool has = lane < m;
+    const uint64_t ent = has ? q[qn - m + lane] : 0;
+    qn = uni(qn - m);
+    __builtin_amdgcn_wave_barrier();
+    if (has) {
+      const uint64_t v = ent & E_MASK;
+      const uint32_t s = (uint32_t)(ent >> 40) & 0xFFFFu;
+      uint32_t d = (uint32_t)(ent >> 56);
+      const uint64_t e = (uint64_t)(s - J.s0) * J.n_per + (v - J.first);
+      if (OP == OP_ZIG64 || OP == OP_MUTATE) {
+        Step st;
+        for (;;) {
+          st = attempt64<KIND>(C.T, C.f64, J.seed, s, v, d, C.dmax);
+          if (st.status != 0) break;
+          d = st.next_d;
+        }
+        double z = st.status == 1 ? st.x : nan64();
+        if (st.status < 0) raise_flag(C.flags, ZG_FLAG_BUDGET);
+        double *out = (double *)J.out;
+        if (OP == OP_MUTATE)
+          out[e] = out[e] + J.sigma * z;
+        else
+          out[e] = z;
+      } else if (OP == OP_ZIG32) {
+        Step32 st;
+        for (;;) {
+          st = attempt32<KIND>(C.T, C.f32, J.seed, s, v, d, C.dmax);
+          if (st.status != 0) break;
+          d = st.next_d;
+        }
+        if (st.status < 0) raise_flag(C.flags, ZG_FLAG_BUDGET);
+        ((float *)J.out)[e] = st.status == 1 ? st.x : nan32();
+      } else {  // OP_POLAR
+        const bool pair = d & 1;
+        d &= ~1u;
+        const uint64_t p = v >> 1;
+        PolarStep st;
+        for (;;) {
+          st = polar_attempt<KIND>(C.T, J.seed, s, p, d, C.dmax);
+          if (st.status != 0) break;
+          d = st.next_d;
+        }
+        if (st.status < 0) {
+          raise_flag(C.flags, ZG_FLAG_BUDGET);
+          st.z1 = st.z2 = nan64();
+        }
+        double *out = (double *)J.out;
+        if (pair) {
+          out[e] = st.z1;
+          out[e + 1] = st.z2;
+        } else {
+          out[e] = (v & 1) ? st.z2 : st.z1;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// --------------------------------------------------------- lane constants
+
+struct LaneConst {
+  uint64_t g[4];    // SplitMix64: gamma * offset of each word of the lane
+  Affine a[4];      // LCG: jump from the chunk base state to each element
+};
+
+template <int OP, int KIND>
+DEV LaneConst lane_constants(const DevTables *T) {
+  LaneConst c;
+  const uint32_t lane = lane_id();
+  for (int t = 0; t < 4; ++t) {
+    c.g[t] = 0;
+    c.a[t] = {1, 0};
+  }
+  if (OP == OP_ZIG32) {
+    // SplitMix64 pair words: word offsets 2*lane and 2*lane+1 (and +2)
+    c.g[0] = GAMMA * (2ull * lane);
+    c.g[1] = GAMMA * (2ull * lane + 1);
+    c.g[2] = GAMMA * (2ull * lane + 2);
+    if (KIND == ZG_JAVA_LCG48) {
+      // element offsets 4*lane + t -> 2 (4 lane + t) steps
+      for (int t = 0; t < 4; ++t) {
+        uint32_t k = 2u * (4u * lane + t);
+        c.a[t] = aff_cat(T->lcg.jump[0][k & 255u], T->lcg.jump[1][k >> 8]);
+      }
+    }
+  } else if (OP == OP_POLAR) {
+    c.g[0] = GAMMA * (uint64_t)lane;   // pair offset
+    if (KIND == ZG_JAVA_LCG48) c.a[0] = T->lcg.jump[0][2u * lane];
+  } else {
+    c.g[0] = GAMMA * (2ull * lane);
+    c.g[1] = GAMMA * (2ull * lane + 1);
+    if (KIND == ZG_JAVA_LCG48) {
+      c.a[0] = T->lcg.jump[0][4u * lane];
+      c.a[1] = T->lcg.jump[0][4u * lane + 2];
+    }
+  }
+  return c;
+}
+
+// ------------------------------------------------------------- tile work
+
+// FP64 fast path of one element: returns the signed candidate and whether the
+// integer test accepted it.
+DEV double fast64(const Fast64 *tab, uint64_t W, bool &fast) {
+  const uint32_t hi = (uint32_t)(W >> 32);
+  const Fast64 f = tab[hi >> 25];
+  const uint64_t j = (W >> 3) & MASK53;
+  fast = j < f.k;
+  return flip_hi((double)j * f.w, hi);
+}
+
+// Processes elements [e_begin, e_end) of job J with one wave, then drains the
+// wave's queue completely.  e_begin is 16-byte aligned in the output and
+// e_end - e_begin is arbitrary.  Elements [0, head) of the job (before the
+// aligned body) are queued first when `with_head`.  Chunks that straddle a
+// stream boundary are queued whole as fresh entries (draw 0): the drain keys
+// each element by itself, so the hot loop never divides.
+template <int OP, int KIND>
+DEV void process_tile(const Job &J, const Ctx &C, const LaneConst &LC, uint64_t *q,
+                      uint64_t e_begin, uint64_t e_end, uint32_t head, bool with_head) {
+  constexpr uint32_t E = (OP == OP_ZIG32) ? 4 : 2;
+  constexpr uint32_t CH = 64 * E;
+  constexpr uint32_t U = (OP == OP_ZIG64 || OP == OP_MUTATE) ? 2 : 1;   // chunks per step
+  constexpr uint32_t STEP = CH * U;
+  constexpr bool LCG = KIND == ZG_JAVA_LCG48;
+  const uint32_t lane = lane_id();
+  e_begin = uni64(e_begin);
+  e_end = uni64(e_end);
+  uint32_t qn = 0;
+  if (with_head && head) {
+    uint32_t hs;
+    uint64_t hv;
+    split(J, lane, hs, hv);
+    qpush2(q, qn, lane < head, qentry(hs, hv, 0), false, 0);
+  }
+  const bool multi = J.n_streams != 1;
+  uint64_t k = 0, r = e_begin;
+  if (multi) {
+    k = uni64(e_begin / J.n_per);
+    r = uni64(e_begin - k * J.n_per);
+  }
+  const uint64_t seed = J.seed;
+  for (uint64_t ec = e_begin; ec < e_end; ec += STEP) {
+    const bool clean = !multi || r + STEP <= J.n_per;
+    const uint32_t s = uni(J.s0 + (uint32_t)k);
+    const uint64_t vc = uni64(J.first + r);
+    const uint64_t e0 = ec + (uint64_t)E * lane;
+    if (!clean) {
+      // straddles a stream boundary: key every element by itself
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u)
+#pragma unroll
+        for (uint32_t t = 0; t < E; t += 2) {
+          const uint64_t ea = e0 + u * CH + t, eb = ea + 1;
+          uint32_t sa, sb;
+          uint64_t va, vb;
+          split(J, ea, sa, va);
+          split(J, eb, sb, vb);
+          qpush2(q, qn, ea < e_end, qentry(sa, va, 0), eb < e_end, qentry(sb, vb, 0));
+        }
+    } else if (OP == OP_ZIG64 || OP == OP_MUTATE) {
+      uint64_t W[2 * U];
+      if (LCG) {
+        uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+          W[2 * u] = lcg_word_from(aff(LC.a[0], Sc));
+          W[2 * u + 1] = lcg_word_from(aff(LC.a[1], Sc));
+          Sc = aff(C.T->lcg.jump[1][1], Sc);   // 256 steps = the next 128-element chunk
+        }
+      } else {
+        const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + vc);
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+          W[2 * u] = mix64(zc + GAMMA * (uint64_t)(u * CH) + LC.g[0]);
+          W[2 * u + 1] = mix64(zc + GAMMA * (uint64_t)(u * CH) + LC.g[1]);
+        }
+      }
+      const bool full = ec + STEP <= e_end;   // wave-uniform: no tail masks needed
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint64_t ea = e0 + u * CH;
+        const bool ok0 = full || ea < e_end, ok1 = full || ea + 1 < e_end;
+        bool fast0, fast1;
+        double x0 = fast64(C.f64, W[2 * u], fast0);
+        double x1 = fast64(C.f64, W[2 * u + 1], fast1);
+        double *out = (double *)J.out + ea;
+        // Every lane stores its whole pair: a slow element gets a placeholder
+        // (the old value for mutation, so the drain can still read it) that
+        // the drain overwrites after a fence.
+        if (OP == OP_MUTATE) {
+          if (ok0 && ok1) {
+            double2 old = *(const double2 *)out;
+            x0 = fast0 ? old.x + J.sigma * x0 : old.x;
+            x1 = fast1 ? old.y + J.sigma * x1 : old.y;
+          } else if (ok0) {
+            double old = out[0];
+            x0 = fast0 ? old + J.sigma * x0 : old;
+          }
+        }
+        if (ok0 && ok1) {
+          *(double2 *)out = make_double2(x0, x1);
+        } else if (ok0) {
+          out[0] = x0;
+        }
+        const uint64_t va = vc + u * CH + 2 * lane;
+        qpush2(q, qn, ok0 && !fast0, qentry(s, va, 0), ok1 && !fast1, qentry(s, va + 1, 0));
+      }
+    } else if (OP == OP_ZIG32) {
+      uint32_t uw[4];
+      if (!LCG) {
+        const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + (vc >> 1));
+        const uint64_t Wa = mix64(zc + LC.g[0]), Wb = mix64(zc + LC.g[1]);
+        if ((vc & 1) == 0) {
+          uw[0] = (uint32_t)(Wa >> 32);
+          uw[1] = (uint32_t)Wa;
+          uw[2] = (uint32_t)(Wb >> 32);
+          uw[3] = (uint32_t)Wb;
+        } else {
+          const uint64_t Wc = mix64(zc + LC.g[2]);
+          uw[0] = (uint32_t)Wa;
+          uw[1] = (uint32_t)(Wb >> 32);
+          uw[2] = (uint32_t)Wb;
+          uw[3] = (uint32_t)(Wc >> 32);
+        }
+      } else {
+        const uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) uw[t] = (uint32_t)(lcg_word_from(aff(LC.a[t], Sc)) >> 32);
+      }
+      float x[4];
+      bool fast[4], ok[4];
+      const bool full = ec + STEP <= e_end;   // wave-uniform: no tail masks needed
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const Fast32 f = C.f32[uw[t] >> 25];
+        const uint32_t j = uw[t] & 0xFFFFFFu;
+        fast[t] = j < f.k;
+        ok[t] = full || e0 + t < e_end;
+        const float xf = (float)j * f.w;
+        x[t] = __int_as_float(__float_as_int(xf) ^ (int)((uw[t] << 7) & 0x80000000u));
+      }
+      float *out = (float *)J.out + e0;
+      if (ok[3]) {
+        *(float4 *)out = make_float4(x[0], x[1], x[2], x[3]);   // slow ones: placeholders
+      } else {
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          if (ok[t]) out[t] = x[t];
+      }
+      const uint64_t va = vc + 4 * lane;
+      qpush2(q, qn, ok[0] && !fast[0], qentry(s, va, 0), ok[1] && !fast[1], qentry(s, va + 1, 0));
+      qpush2(q, qn, ok[2] && !fast[2], qentry(s, va + 2, 0), ok[3] && !fast[3],
+             qentry(s, va + 3, 0));
+    } else {  // OP_POLAR
+      const bool ok0 = e0 < e_end, ok1 = e0 + 1 < e_end;
+      const bool paired = (vc & 1) == 0 && ok1;   // vc parity is wave-uniform
+      const uint64_t va = vc + 2 * lane;
+      bool push_a, push_b = false;
+      uint64_t ent_a, ent_b = 0;
+      if (paired) {
+        // pair p = vc/2 + lane, attempt 0: draws 0 and 1
+        uint64_t W1, W2;
+        if (LCG) {
+          uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc >> 1, 0) + 1);
+          uint64_t S1 = aff(LC.a[0], Sc);
+          W1 = lcg_word_from(S1);
+          W2 = lcg_word_from(aff(C.T->lcg.window[1], S1));
+        } else {
+          const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + (vc >> 1));
+          const uint64_t z = zc + LC.g[0];
+          W1 = mix64(z);
+          W2 = mix64(z + (GAMMA << 40));
+        }
+        const PolarStep st = polar_from_words(W1, W2, 0);
+        const bool acc = st.status == 1 && C.dmax >= 2;
+        *(double2 *)((double *)J.out + e0) = make_double2(st.z1, st.z2);   // placeholder if rejected
+        push_a = !acc;
+        ent_a = qentry(s, va, (st.status == 1 ? 0u : 2u) | 1u);   // low bit: both elements
+      } else {
+        push_a = ok0;
+        ent_a = qentry(s, va, 0);
+        push_b = ok1;
+        ent_b = qentry(s, va + 1, 0);
+      }
+      qpush2(q, qn, push_a, ent_a, push_b, ent_b);
+    }
+    if (qn > (uint32_t)(QCAP - STEP)) drain<OP, KIND>(J, C, q, qn, 63);
+    r += STEP;
+    if (multi)
+      while (r >= J.n_per) {
+        r -= J.n_per;
+        ++k;
+      }
+  }
+  drain<OP, KIND>(J, C, q, qn, 0);
+}
+
+// Loads the fast tables into LDS (whole block; ends with a barrier).
+DEV void load_fast(const DevTables *T, Fast64 *f64, Fast32 *f32, bool need64, bool need32) {
+  for (uint32_t i = threadIdx.x; i < ZG_LAYERS; i += blockDim.x) {
+    if (need64) f64[i] = T->fast64[i];
+    if (need32) f32[i] = T->fast32[i];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- kernels
+
+// One tile per wave.  Tile t covers [head + t*tile, head + (t+1)*tile).
+template <int OP, int KIND>
+__global__ __launch_bounds__(1024) void k_fill(Job J, const DevTables *__restrict__ T,
+                                               uint32_t dmax, uint32_t *flags, uint32_t tile,
+                                               uint32_t head) {
+  __shared__ Fast64 s_f64[ZG_LAYERS];
+  __shared__ Fast32 s_f32[ZG_LAYERS];
+  extern __shared__ uint64_t s_q[];   // waves x QCAP
+  load_fast(T, s_f64, s_f32, OP != OP_ZIG32, OP == OP_ZIG32);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  const uint64_t b = head + gw * tile;
+  Ctx C{T, s_f64, s_f32, dmax, flags};
+  if (b < J.n_total || (gw == 0 && head)) {
+    LaneConst LC = lane_constants<OP, KIND>(T);
+    uint64_t e_end = b + tile < J.n_total ? b + tile : J.n_total;
+    uint64_t e_begin = b < e_end ? b : e_end;
+    process_tile<OP, KIND>(J, C, LC, s_q + wave * QCAP, e_begin, e_end, head, gw == 0);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_words(uint64_t *out, uint64_t n, const DevTables *T,
+                                               uint32_t kind, uint64_t seed, uint32_t s,
+                                               uint32_t d, uint64_t first) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  if (kind == ZG_JAVA_LCG48) {
+    // per-thread jump-ahead to the first index, then a constant stride map
+    if (i >= n) return;
+    const uint64_t S0 = lcg_state0(seed);
+    uint64_t S1 = lcg_jump(&T->lcg, S0, 2 * lcg_index(s, first + i, d) + 1);
+    Affine step = {1, 0};
+    {
+      // 2*stride steps, composed from the byte tables once per thread
+      uint64_t k = 2 * stride;
+      for (int b = 0; b < LCG_JUMP_BYTES; ++b) {
+        uint32_t x = (uint32_t)(k >> (8 * b)) & 255u;
+        if (x) step = aff_cat(step, T->lcg.jump[b][x]);
+      }
+    }
+    for (; i < n; i += stride) {
+      out[i] = lcg_word_from(S1);
+      S1 = aff(step, S1);
+    }
+  } else {
+    for (; i < n; i += stride) out[i] = sm64_word(seed, s, first + i, d);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_decide(const uint64_t *words, uint64_t n,
+                                                const DevTables *T, uint8_t *cls, double *x) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t W = words[i];
+  uint32_t li = (uint32_t)(W >> 57);
+  uint64_t j = (W >> 3) & MASK53;
+  Fast64 f = T->fast64[li];
+  x[i] = flip((double)j * f.w, (W >> 56) & 1);
+  cls[i] = j < f.k ? 0 : (li == 0 ? 2 : 1);
+}
+
+// Resolves counter-keyed requests in submission order: every request reads
+// its handle's counter as it stood before the batch, adds its offset among the
+// batch's earlier requests of that handle, then the last request of each
+// handle advances the counter.  One workgroup, two phases.
+__global__ __launch_bounds__(1024) void k_reserve(DevRequest *R, const BatchHeader *H,
+                                                  uint64_t *counters, uint32_t *flags) {
+  const uint32_t nreq = H->nreq;
+  for (uint32_t i = threadIdx.x; i < nreq; i += blockDim.x) {
+    DevRequest &r = R[i];
+    if (r.handle >= 0) {
+      uint64_t first = counters[r.handle] + r.off;
+      r.job.first = first;
+      if (first + r.job.n_total > r.limit || first + r.job.n_total < first) {
+        r.status = ZG_FLAG_RANGE;
+        atomicOr(flags, ZG_FLAG_RANGE);
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nreq; i += blockDim.x) {
+    const DevRequest &r = R[i];
+    if (r.handle >= 0 && r.last_of_handle) counters[r.handle] = r.job.first + r.job.n_total;
+  }
+}
+
+// Persistent batch kernel: waves take tiles t = gw, gw + W, ... of the
+// concatenated tile space; each tile belongs to one request (found by binary
+// search over tile0), so the branch on its op is uniform.  The wave that
+// finishes a request's last tile writes its completion word.
+__global__ __launch_bounds__(512) void k_batch(DevRequest *R, const BatchHeader *H,
+                                                const DevTables *__restrict__ T,
+                                                uint32_t *flags) {
+  __shared__ Fast64 s_f64[ZG_LAYERS];
+  __shared__ Fast32 s_f32[ZG_LAYERS];
+  extern __shared__ uint64_t s_q[];   // waves x QCAP
+  load_fast(T, s_f64, s_f32, true, true);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  const uint32_t nreq = H->nreq;
+  const uint64_t total = H->total_tiles;
+  const uint32_t dmax = H->dmax;
+  Ctx C{T, s_f64, s_f32, dmax, flags};
+  for (uint64_t t = gw; t < total; t += nw) {
+    // the request with tile0 <= t < tile0 + tiles (every request has >= 1 tile)
+    uint32_t lo = 0, hi = nreq;
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (R[mid].tile0 <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const uint32_t ri = __builtin_amdgcn_readfirstlane(lo);
+    DevRequest &rq = R[ri];
+    const Job J = rq.job;
+    const uint64_t lt = t - rq.tile0;
+    if (rq.status == 0) {
+      const uint64_t b = rq.head + lt * rq.tile;
+      uint64_t e_end = b + rq.tile < J.n_total ? b + rq.tile : J.n_total;
+      uint64_t e_begin = b < e_end ? b : e_end;
+#define ZG_TILE_CASE(OPV)                                                                  \
+  case OPV: {                                                                              \
+    if (J.kind == ZG_JAVA_LCG48) {                                                         \
+      LaneConst LC = lane_constants<OPV, ZG_JAVA_LCG48>(T);                                \
+      process_tile<OPV, ZG_JAVA_LCG48>(J, C, LC, s_q + wave * QCAP, e_begin, e_end, rq.head, \
+                                       lt == 0);                                           \
+    } else {                                                                               \
+      LaneConst LC = lane_constants<OPV, ZG_SPLITMIX64>(T);                                \
+      process_tile<OPV, ZG_SPLITMIX64>(J, C, LC, s_q + wave * QCAP, e_begin, e_end, rq.head, \
+                                       lt == 0);                                           \
+    }                                                                                      \
+  } break;
+      switch (J.op) {
+        ZG_TILE_CASE(OP_ZIG64)
+        ZG_TILE_CASE(OP_ZIG32)
+        ZG_TILE_CASE(OP_POLAR)
+        ZG_TILE_CASE(OP_MUTATE)
+        default: break;
+      }
+#undef ZG_TILE_CASE
+    }
+    // completion: make this wave's stores visible, count the tile down
+    __threadfence();
+    if (lane_id() == 0) {
+      uint32_t before = atomicSub(&rq.remaining, 1u);
+      if (before == 1 && rq.done_flag) {
+        __threadfence_system();
+        uint32_t val = rq.done_value | (rq.status ? 0x80000000u : 0u);
+        __hip_atomic_store(rq.done_flag, val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ host launch
+
+template <int OP, int KIND>
+static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
+                                 uint32_t tile, uint32_t waves, uint32_t head,
+                                 hipStream_t stream) {
+  uint64_t body = J.n_total > head ? J.n_total - head : 0;
+  uint64_t tiles = (body + tile - 1) / tile;
+  if (tiles == 0) tiles = 1;   // head-only jobs still need wave 0
+  uint64_t blocks = (tiles + waves - 1) / waves;
+  hipLaunchKernelGGL((k_fill<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * waves),
+                     (size_t)waves * QCAP * sizeof(uint64_t), stream, J, T, dmax, flags, tile, head);
+  return hipGetLastError();
+}
+
+template <int OP>
+static hipError_t launch_kind(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
+                              uint32_t tile, uint32_t waves, uint32_t head, hipStream_t stream) {
+  if (J.kind == ZG_JAVA_LCG48)
+    return launch_fill_op<OP, ZG_JAVA_LCG48>(J, T, dmax, flags, tile, waves, head, stream);
+  return launch_fill_op<OP, ZG_SPLITMIX64>(J, T, dmax, flags, tile, waves, head, stream);
+}
+
+hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
+                       uint32_t tile, uint32_t waves, uint32_t head, hipStream_t stream) {
+  switch (J.op) {
+    case OP_ZIG64: return launch_kind<OP_ZIG64>(J, T, dmax, flags, tile, waves, head, stream);
+    case OP_ZIG32: return launch_kind<OP_ZIG32>(J, T, dmax, flags, tile, waves, head, stream);
+    case OP_POLAR: return launch_kind<OP_POLAR>(J, T, dmax, flags, tile, waves, head, stream);
+    default: return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, stream);
+  }
+}
+
+hipError_t launch_words(uint64_t *out, uint64_t n, const DevTables *T, uint32_t kind,
+                        uint64_t seed, uint32_t s, uint32_t d, uint64_t first,
+                        hipStream_t stream) {
+  uint64_t threads = n < (1ull << 22) ? n : (1ull << 22);
+  uint32_t blocks = (uint32_t)((threads + 255) / 256);
+  hipLaunchKernelGGL(k_words, dim3(blocks), dim3(256), 0, stream, out, n, T, kind, seed, s, d,
+                     first);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, uint8_t *cls,
+                         double *x, hipStream_t stream) {
+  uint32_t blocks = (uint32_t)((n + 255) / 256);
+  hipLaunchKernelGGL(k_decide, dim3(blocks), dim3(256), 0, stream, words, n, T, cls, x);
+  return hipGetLastError();
+}
+
+const void *kernel_reserve() { return (const void *)k_reserve; }
+const void *kernel_batch() { return (const void *)k_batch; }
+size_t batch_lds_bytes(uint32_t waves) { return (size_t)waves * QCAP * sizeof(uint64_t); }
+
+}  // namespace zg

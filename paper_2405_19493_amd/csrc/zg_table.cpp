@@ -1,0 +1,245 @@
+// Host-side construction of the 128-layer ziggurat table in double-double
+// arithmetic, and of the java.util.Random jump-ahead tables.
+//
+// Table (Section 1 / Section 2 "Ziggurat": the GSL-style original ziggurat of
+// Marsaglia-Tsang and Leong, 128 equal-area layers): f(x) = exp(-x^2/2);
+// v = r f(r) + f(r)/r; b_0 = r, b_i = f^-1(f(b_{i-1}) + v/b_{i-1}); r is the
+// root of the closure f(b_126) + v/b_126 = 1.  Every entry handed to the
+// kernels is the correctly rounded value of the exact quantity: the
+// double-double evaluation carries about 100 bits, so rounding it to 53 (or
+// 24) bits is exact except for values within 2^-100 of a rounding boundary.
+//
+// Compiled with -ffp-contract=off: the error-free transformations below
+// depend on every product and sum being rounded separately.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "zg_internal.h"
+
+namespace zg {
+namespace {
+
+struct dd {
+  double hi, lo;
+};
+
+inline dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+inline dd fast_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+inline dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, std::fma(a, b, -p)};
+}
+inline dd mk(double a) { return {a, 0.0}; }
+inline dd add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+inline dd neg(dd a) { return {-a.hi, -a.lo}; }
+inline dd sub(dd a, dd b) { return add(a, neg(b)); }
+inline dd mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p.hi, p.lo);
+}
+inline dd mul_pow2(dd a, double p2) { return {a.hi * p2, a.lo * p2}; }
+inline dd divide(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd r = sub(a, mul(b, mk(q1)));
+  double q2 = r.hi / b.hi;
+  r = sub(r, mul(b, mk(q2)));
+  double q3 = r.hi / b.hi;
+  return add(fast_two_sum(q1, q2), mk(q3));
+}
+inline bool lt(dd a, dd b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+
+// sqrt by one Newton correction of the double root: s = x + (a - x^2)/(2x).
+dd dd_sqrt(dd a) {
+  if (a.hi <= 0.0) return mk(0.0);
+  double x = std::sqrt(a.hi);
+  dd r = sub(a, mul(mk(x), mk(x)));
+  return add(mk(x), mk(r.hi / (2.0 * x)));
+}
+
+// ln 2 to about 107 bits.
+const dd LN2 = {0x1.62e42fefa39efp-1, 0x1.abc9e3b39803fp-56};
+
+// exp: a = k ln2 + t, |t| <= ln2/2; t' = t/2^10; expm1(t') by its Taylor
+// series; undo the scaling with e <- 2e + e^2 (keeps relative accuracy of
+// expm1), then 1 + e and the power of two.
+dd dd_exp(dd a) {
+  double k = std::nearbyint(a.hi / LN2.hi);
+  dd t = sub(a, mul(LN2, mk(k)));
+  t = mul_pow2(t, 1.0 / 1024.0);
+  dd term = t, sum = t;
+  for (int n = 2; n <= 14; ++n) {
+    term = divide(mul(term, t), mk((double)n));
+    sum = add(sum, term);
+    if (std::fabs(term.hi) < 1e-36) break;
+  }
+  for (int i = 0; i < 10; ++i) sum = add(mul_pow2(sum, 2.0), mul(sum, sum));
+  dd e = add(sum, mk(1.0));
+  int ki = (int)k;
+  return {std::ldexp(e.hi, ki), std::ldexp(e.lo, ki)};
+}
+
+// log: two Newton steps y <- y + a exp(-y) - 1 from the double logarithm.
+dd dd_log(dd a) {
+  dd y = mk(std::log(a.hi));
+  for (int it = 0; it < 2; ++it) y = add(y, sub(mul(a, dd_exp(neg(y))), mk(1.0)));
+  return y;
+}
+
+dd f_of(dd x) { return dd_exp(mul_pow2(neg(mul(x, x)), 0.5)); }
+dd finv(dd y) { return dd_sqrt(mul_pow2(neg(dd_log(y)), 2.0)); }
+
+// v(r) = r f(r) + f(r)/r: the base box plus the exponential majorant's mass.
+dd area_of(dd r) {
+  dd fr = f_of(r);
+  return add(mul(r, fr), divide(fr, r));
+}
+
+// Closure residual: > 0 when the layers reach the top too early (r too
+// small), otherwise f(b_126) + v/b_126 - 1 (decreasing in r).
+dd closure(dd r) {
+  dd v = area_of(r);
+  dd b = r;
+  for (int i = 1; i < ZG_LAYERS - 1; ++i) {
+    dd t = add(f_of(b), divide(v, b));
+    if (!lt(t, mk(1.0))) return mk(1.0);
+    b = finv(t);
+  }
+  return sub(add(f_of(b), divide(v, b)), mk(1.0));
+}
+
+// Correctly rounded double of a dd value: the normalising sum hi + lo is
+// itself rounded to nearest (an exact tie is left to ties-to-even; the dd
+// value is then within 2^-100 of the midpoint and no rounding is certain).
+double rn64(dd x) { return fast_two_sum(x.hi, x.lo).hi; }
+
+// Correctly rounded float of a dd value.
+float rn32(dd x) {
+  dd n = fast_two_sum(x.hi, x.lo);
+  float f = (float)n.hi;   // round-to-nearest-even of hi
+  float fu = std::nextafter(f, INFINITY), fd = std::nextafter(f, -INFINITY);
+  double mu = ((double)f + (double)fu) * 0.5, md = ((double)f + (double)fd) * 0.5;
+  if (n.hi == mu && n.lo > 0) return fu;
+  if (n.hi == md && n.lo < 0) return fd;
+  if (n.hi == mu && n.lo < 0) return f;
+  if (n.hi == md && n.lo > 0) return f;
+  return f;
+}
+
+// floor of a non-negative dd value (below 2^63).
+uint64_t floor_u64(dd x) {
+  dd n = fast_two_sum(x.hi, x.lo);
+  double fl = std::floor(n.hi);
+  if (fl == n.hi) {
+    if (n.lo < 0) return (uint64_t)fl - 1;
+    return (uint64_t)fl + (uint64_t)std::floor(n.lo);
+  }
+  return (uint64_t)fl;
+}
+
+}  // namespace
+
+zg_status build_table(zg_table_view *t) {
+  // bisection for r on [0.5, 5]: 110 halvings reach double-double resolution
+  dd lo = mk(0.5), hi = mk(5.0);
+  for (int it = 0; it < 110; ++it) {
+    dd mid = mul_pow2(add(lo, hi), 0.5);
+    if (closure(mid).hi > 0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  dd r = mul_pow2(add(lo, hi), 0.5);
+  dd v = area_of(r);
+  dd b[ZG_LAYERS];
+  b[0] = r;
+  for (int i = 1; i < ZG_LAYERS - 1; ++i) b[i] = finv(add(f_of(b[i - 1]), divide(v, b[i - 1])));
+  b[ZG_LAYERS - 1] = mk(0.0);
+  dd W[ZG_LAYERS], y[ZG_LAYERS], q[ZG_LAYERS];
+  W[0] = divide(v, f_of(r));
+  for (int i = 1; i < ZG_LAYERS; ++i) W[i] = b[i - 1];
+  for (int i = 0; i < ZG_LAYERS; ++i) q[i] = divide(b[i], W[i]);
+  for (int i = 0; i < ZG_LAYERS - 1; ++i) y[i] = f_of(b[i]);
+  y[ZG_LAYERS - 1] = mk(1.0);
+
+  std::memset(t, 0, sizeof(*t));
+  t->r = rn64(r);
+  t->v = rn64(v);
+  for (int i = 0; i < ZG_LAYERS; ++i) {
+    t->W[i] = rn64(W[i]);
+    t->y[i] = rn64(y[i]);
+    t->dy[i] = i == 0 ? 0.0 : rn64(sub(y[i], y[i - 1]));
+    t->k53[i] = floor_u64(mul_pow2(q[i], 0x1p53));
+    t->k24[i] = (uint32_t)floor_u64(mul_pow2(q[i], 0x1p24));
+    t->w53[i] = t->W[i] * 0x1p-53;
+    t->w24d[i] = t->W[i] * 0x1p-24;
+    t->w24[i] = rn32(W[i]) * 0x1p-24f;
+  }
+  // sanity of the geometry: equal areas to 1e-12 in plain double arithmetic
+  for (int i = 1; i < ZG_LAYERS; ++i) {
+    double area = t->W[i] * t->dy[i];
+    if (!(std::fabs(area - t->v) <= 1e-12 * t->v)) return ZG_EINVAL;
+  }
+  if (!(std::fabs(t->W[0] * t->y[0] - t->v) <= 1e-12 * t->v)) return ZG_EINVAL;
+  return ZG_OK;
+}
+
+// ---------------------------------------------------------------- LCG tables
+
+static inline Affine compose(Affine first, Affine second) {
+  // apply `first`, then `second`: S -> A2 (A1 S + C1) + C2
+  return {(second.A * first.A) & LCG_M48, (second.A * first.C + second.C) & LCG_M48};
+}
+
+Affine lcg_power(uint64_t k) {
+  Affine result = {1, 0};
+  Affine base = {LCG_A, LCG_C};
+  while (k) {
+    if (k & 1) result = compose(result, base);
+    base = compose(base, base);
+    k >>= 1;
+  }
+  return result;
+}
+
+void build_lcg_tables(LcgTables *L) {
+  // jump[b][x] = x * 256^b steps, built by repeated composition
+  for (int b = 0; b < LCG_JUMP_BYTES; ++b) {
+    Affine unit = lcg_power(1ull << (8 * b));
+    Affine acc = {1, 0};
+    for (int x = 0; x < 256; ++x) {
+      L->jump[b][x] = acc;
+      acc = compose(acc, unit);
+    }
+  }
+  // window[d] = 2 d LCG_WINDOW steps (draw d of the same variate)
+  Affine w1 = lcg_power(2 * ZG_LCG_WINDOW);
+  Affine acc = {1, 0};
+  for (int d = 0; d < 256; ++d) {
+    L->window[d] = acc;
+    acc = compose(acc, w1);
+  }
+}
+
+}  // namespace zg
+
+extern "C" zg_status zg_build_table(zg_table_view *out) {
+  if (!out) return ZG_EINVAL;
+  return zg::build_table(out);
+}

@@ -21,3 +21,20 @@ def orc():
     from oracle import coracle
     coracle.build(force=False)
     return coracle
+
+
+@pytest.fixture(scope="session")
+def zg():
+    """The HIP library through its Python binding (GPU tests only)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_19493_amd as Z
+    return Z
+
+
+@pytest.fixture(scope="session")
+def ctx(zg):
+    c = zg.Context(0)
+    yield c
+    c.close()
