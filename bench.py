@@ -37,7 +37,22 @@ def parse():
                    help="restrict the timed kernels (for profiling runs)")
     p.add_argument("--serve-seconds", type=float, default=0.0,
                    help="also run the serving loop for this long and report p50/p99")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run three plain 1 GiB device copies (the known-size kernel "
+                        "that scales the HBM byte counters) and exit")
     return p.parse_args()
+
+
+def copy_calibration(torch):
+    """Three device-to-device copies of 2^27 float64 (1 GiB read + 1 GiB written
+    each): what FETCH_SIZE and WRITE_SIZE read for them calibrates those
+    counters for the fill kernels."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": a.numel() * 8, "launches": 3}), flush=True)
 
 
 def time_kernel(fn, steps, warmup, torch):
@@ -60,27 +75,31 @@ def time_kernel(fn, steps, warmup, torch):
 
 
 def cpu_baseline(seconds):
-    """The oracle (oracle/zg_oracle.c, threaded over index chunks) on a bounded
-    sample of the same workload: whole streams of 4096 variates, seed 7,
-    SplitMix64, until about `seconds` of wall time have passed."""
-    import numpy as np  # noqa: F401
+    """The oracle (oracle/zg_oracle.c) on a bounded sample of the same workload:
+    whole streams of 4096 variates, seed 7, SplitMix64, one stream per call, the
+    calls spread over a thread pool of the host's cores (capped at 16, the CPU
+    share of one GPU), until about `seconds` of wall time have passed."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import coracle as orc
     orc.build(force=False)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 64))
-    done = 0
+    cores = max(1, min(cores, 16))
+    per_batch = 64 * cores
+
+    def one(s):
+        orc.fill_f64(orc.SM64, SEED, s, 0, N_PER, nthreads=1)
+
     s = 0
     t0 = time.perf_counter()
-    chunk_streams = 256
-    while time.perf_counter() - t0 < seconds and s < N_STREAMS:
-        for k in range(chunk_streams):
-            orc.fill_f64(orc.SM64, SEED, s + k, 0, N_PER, nthreads=cores)
-        s += chunk_streams
-        done += chunk_streams * N_PER
+    with ThreadPoolExecutor(max_workers=cores) as pool:
+        while time.perf_counter() - t0 < seconds and s < N_STREAMS:
+            list(pool.map(one, range(s, min(s + per_batch, N_STREAMS))))
+            s = min(s + per_batch, N_STREAMS)
     dt = time.perf_counter() - t0
+    done = s * N_PER
     return {"value": done / dt, "unit": "variates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{s} of the 65536 streams x 4096 FP64 ziggurat variates "
-                      f"(SplitMix64 seed 7), {done} variates in {dt:.1f} s"}
+            "sample": f"streams 0..{s - 1} of the 65536 x 4096 FP64 ziggurat variates "
+                      f"(SplitMix64 seed 7): {done} variates in {dt:.1f} s"}
 
 
 def read_traffic(kernel):
@@ -112,6 +131,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import paper_2405_19493_amd as Z
 
     n = N_STREAMS * N_PER

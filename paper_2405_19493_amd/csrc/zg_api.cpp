@@ -220,6 +220,7 @@ zg_status zg_fill_streams(zg_ctx *ctx, void *d_out, uint64_t n_per_stream, uint3
   J.first = first_index;
   J.seed = seed;
   J.sigma = 0.0;
+  J.inv_n_per = 1.0 / (double)n_per_stream;
   J.s0 = stream0;
   J.n_streams = n_streams;
   J.kind = kind;
@@ -248,6 +249,7 @@ zg_status zg_mutate(zg_ctx *ctx, double *d_x, uint64_t n, double sigma, zg_kind 
   J.first = first_index;
   J.seed = seed;
   J.sigma = sigma;
+  J.inv_n_per = 1.0 / (double)n;
   J.s0 = stream;
   J.n_streams = 1;
   J.kind = kind;
@@ -427,7 +429,7 @@ zg_status zg_get_tune(const zg_ctx *ctx, int cls, zg_tune *out) {
 zg_status zg_set_tune(zg_ctx *ctx, int cls, const zg_tune *in) {
   if (!ctx || !in || cls < 0 || cls >= ZG_TUNE_CLASSES) return ZG_EINVAL;
   uint32_t ch = cls == ZG_TUNE_FILL_F32 ? 256u : 128u;
-  if (in->tile == 0 || in->tile % ch || in->tile > (1u << 20)) return ZG_EINVAL;
+  if (in->tile == 0 || in->tile % ch || in->tile > (1u << 19)) return ZG_EINVAL;
   if (in->waves_per_block < 1 || in->waves_per_block > 16) return ZG_EINVAL;
   if (in->batch_blocks_per_cu < 1 || in->batch_blocks_per_cu > 8) return ZG_EINVAL;
   if (cls == ZG_TUNE_BATCH && (in->tile % 256 || in->waves_per_block > 8)) return ZG_EINVAL;

@@ -65,6 +65,7 @@ zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
     d.job.first = r.first_index;
     d.job.seed = seed;
     d.job.sigma = r.sigma;
+    d.job.inv_n_per = 1.0 / (double)r.n;
     d.job.s0 = stream;
     d.job.n_streams = 1;
     d.job.kind = kind;

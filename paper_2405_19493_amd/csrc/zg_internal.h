@@ -60,6 +60,7 @@ struct Job {
   uint64_t first;
   uint64_t seed;
   double sigma;
+  double inv_n_per;   // RN(1 / n_per): element -> stream split on rare paths
   uint32_t s0;
   uint32_t n_streams;
   uint32_t kind;

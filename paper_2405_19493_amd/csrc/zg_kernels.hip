@@ -24,8 +24,7 @@ namespace zg {
 #define DEV __device__ __forceinline__
 
 constexpr uint64_t MASK53 = (1ull << 53) - 1;
-constexpr int QCAP = 320;              // queue entries per wave (>= 63 + largest step)
-constexpr uint64_t E_MASK = (1ull << 40) - 1;
+constexpr int QCAP = 1088;             // main queue entries per wave (>= 63 + one flush)
 
 // ------------------------------------------------------------ uniform words
 
@@ -65,6 +64,16 @@ DEV uint64_t lcg_index(uint32_t s, uint64_t v, uint32_t d) {
 DEV uint64_t lcg_word_from(uint64_t S1) {
   uint64_t S2 = (LCG_A * S1 + LCG_C) & LCG_M48;
   return (((S1 >> 22) << 27) + (S2 >> 21)) << 11;
+}
+
+// Exact conversion of an integer below 2^53: hi * 2^32 + lo is representable,
+// so the fused multiply-add rounds nothing.
+// (The empty asm keeps the high half an opaque 32-bit value; otherwise the
+// compiler widens the conversion back to 64 bits and adds a zero.)
+DEV double to_f64(uint64_t j) {
+  uint32_t hi = (uint32_t)(j >> 32);
+  asm volatile("" : "+v"(hi));
+  return fma((double)hi, 4294967296.0, (double)(uint32_t)j);
 }
 
 DEV double u53(uint64_t W) { return (double)(W >> 11) * 0x1p-53; }
@@ -122,7 +131,7 @@ DEV Step attempt64(const DevTables *T, const Fast64 *fast, uint64_t seed, uint32
   uint32_t i = (uint32_t)(W >> 57);
   Fast64 f = fast[i];
   uint64_t j = (W >> 3) & MASK53;
-  double x = (double)j * f.w;
+  double x = to_f64(j) * f.w;
   Step st;
   if (j < f.k)
     st = {1, x, d};
@@ -130,6 +139,18 @@ DEV Step attempt64(const DevTables *T, const Fast64 *fast, uint64_t seed, uint32
     st = slow_step<KIND>(T, seed, s, v, d, dmax, i, x);
   if (st.status == 1) st.x = flip(st.x, (W >> 56) & 1);
   return st;
+}
+
+// Fast test only of the attempt at draw d: 1 accepted, 0 not fast, -1 budget.
+template <int KIND>
+DEV Step fast_only64(const DevTables *T, const Fast64 *fast, uint64_t seed, uint32_t s,
+                     uint64_t v, uint32_t d, uint32_t dmax) {
+  if (d >= dmax) return {-1, 0.0, d};
+  uint64_t W = wordk<KIND>(T, seed, s, v, d);
+  Fast64 f = fast[(uint32_t)(W >> 57)];
+  uint64_t j = (W >> 3) & MASK53;
+  if (j < f.k) return {1, flip(to_f64(j) * f.w, (W >> 56) & 1), d};
+  return {0, 0.0, d};
 }
 
 struct Step32 {
@@ -146,6 +167,20 @@ DEV uint32_t word32(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, u
     return (v & 1) ? (uint32_t)W : (uint32_t)(W >> 32);
   }
   return (uint32_t)(wordk<KIND>(T, seed, s, v, d) >> 32);
+}
+
+template <int KIND>
+DEV Step32 fast_only32(const DevTables *T, const Fast32 *fast, uint64_t seed, uint32_t s,
+                       uint64_t v, uint32_t d, uint32_t dmax) {
+  if (d >= dmax) return {-1, 0.f, d};
+  uint32_t u = word32<KIND>(T, seed, s, v, d);
+  Fast32 f = fast[u >> 25];
+  uint32_t j = u & 0xFFFFFFu;
+  if (j < f.k) {
+    float xf = (float)j * f.w;
+    return {1, ((u >> 24) & 1) ? -xf : xf, d};
+  }
+  return {0, 0.f, d};
 }
 
 template <int KIND>
@@ -204,17 +239,17 @@ DEV uint64_t uni64(uint64_t x) {
   return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
 }
 
-// Queue entry: variate index v (40 bits), stream s (16 bits), draw d (8 bits).
-// The element index is (s - s0) n_per + (v - first): no division on drain.
-// Polar entries hold an even draw; its low bit marks "both elements of the pair".
-DEV uint64_t qentry(uint32_t s, uint64_t v, uint32_t d) {
-  return v | ((uint64_t)s << 40) | ((uint64_t)d << 56);
-}
+// Queue entry (32 bits): element offset from the tile base (21 bits), draw d
+// of the next attempt (8 bits), flags (3 bits; F_PAIR: polar entry covering
+// both elements of a pair).
+constexpr uint32_t OFF_MASK = (1u << 21) - 1;
+constexpr uint32_t F_PAIR = 1u;
+DEV uint32_t qent(uint32_t off, uint32_t d, uint32_t fl) { return off | (d << 21) | (fl << 29); }
 
 // Appends up to two entries per lane (a, then b).  Wave-uniform control flow
 // only: the queue count qn is the same in every lane.
-DEV void qpush2(uint64_t *q, uint32_t &qn, bool pa, uint64_t ea, bool pb, uint64_t eb) {
-  const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+DEV void qpush2(uint32_t *q, uint32_t &qn, bool pa, uint32_t ea, bool pb, uint32_t eb) {
+  const uint64_t ma = __builtin_amdgcn_ballot_w64(pa), mb = __builtin_amdgcn_ballot_w64(pb);
   if ((ma | mb) != 0) {
     const uint32_t base = qn + prefix_below(ma) + prefix_below(mb);
     if (pa) q[base] = ea;
@@ -224,17 +259,26 @@ DEV void qpush2(uint64_t *q, uint32_t &qn, bool pa, uint64_t ea, bool pb, uint64
   }
 }
 
-// Element e of a job -> (stream, variate index).  Divides: used only for the
-// alignment head and for chunks that straddle a stream boundary.
+// Element e of a job -> (stream, variate index).  Rare paths only (drain):
+// the quotient from the reciprocal is within one of the true one (e < 2^40),
+// and one correction step fixes it.
 DEV void split(const Job &J, uint64_t e, uint32_t &s, uint64_t &v) {
   if (J.n_streams == 1) {
     s = J.s0;
     v = J.first + e;
-  } else {
-    uint64_t k = e / J.n_per;
-    s = J.s0 + (uint32_t)k;
-    v = J.first + (e - k * J.n_per);
+    return;
   }
+  uint64_t k = (uint64_t)((double)e * J.inv_n_per);
+  int64_t r = (int64_t)(e - k * J.n_per);
+  if (r < 0) {
+    k -= 1;
+    r += (int64_t)J.n_per;
+  } else if ((uint64_t)r >= J.n_per) {
+    k += 1;
+    r -= (int64_t)J.n_per;
+  }
+  s = J.s0 + (uint32_t)k;
+  v = J.first + (uint64_t)r;
 }
 
 struct Ctx {
@@ -256,64 +300,230 @@ DEV double flip_hi(double x, uint32_t whi) {
 }
 
 // ------------------------------------------------------------ queue drain
+//
+// Each wave owns two LDS lists of 32-bit entries (offset from the tile base,
+// draw index, flags): the main queue of variates whose attempt failed the fast
+// test, and a short list of attempts that landed in the base layer beyond r
+// (the tail step, with a log and an exp, is much longer than the wedge step,
+// so tails are run together once per tile instead of in most rounds).
 
-// Processes queued variates 64 at a time until at most `keep` remain; each
-// lane loops over attempts of its own variate until acceptance or the budget
-// (the loop always ends: every rejection advances the draw index by >= 2).
+constexpr uint32_t TCAP = 128;   // tail list entries per wave
+
+struct Queues {
+  uint32_t *q;    // main queue, QCAP entries
+  uint32_t *t;    // tail list, TCAP entries
+  uint32_t qn;    // wave-uniform counts
+  uint32_t tn;
+};
+
+// Decoded first word of an attempt at draw d.
+struct Att {
+  uint32_t cls;    // 0 fast, 1 wedge, 2 tail
+  uint32_t i;
+  uint32_t neg;
+  double x;        // candidate (FP64; FP32 mode: j * w24d[i], slow path only)
+  float xf;        // FP32 mode: fast-path value (unsigned)
+};
+
 template <int OP, int KIND>
-DEV void drain(const Job &J, const Ctx &C, uint64_t *q, uint32_t &qn, uint32_t keep) {
+DEV Att decode_attempt(const Ctx &C, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  Att a;
+  if (OP == OP_ZIG32) {
+    const uint32_t u = word32<KIND>(C.T, seed, s, v, d);
+    a.i = u >> 25;
+    a.neg = (u >> 24) & 1;
+    const uint32_t j = u & 0xFFFFFFu;
+    const Fast32 f = C.f32[a.i];
+    a.xf = (float)j * f.w;
+    a.x = (double)j * C.T->w24d[a.i];
+    a.cls = j < f.k ? 0u : (a.i ? 1u : 2u);
+  } else {
+    const uint64_t W = wordk<KIND>(C.T, seed, s, v, d);
+    a.i = (uint32_t)(W >> 57);
+    a.neg = (uint32_t)(W >> 56) & 1;
+    const uint64_t j = (W >> 3) & MASK53;
+    const Fast64 f = C.f64[a.i];
+    a.x = to_f64(j) * f.w;
+    a.xf = 0.f;
+    a.cls = j < f.k ? 0u : (a.i ? 1u : 2u);
+  }
+  return a;
+}
+
+// Writes an accepted value (x is the unsigned FP64 candidate, or for an FP32
+// fast path, xf) or the budget NaN.
+template <int OP>
+DEV void finish(const Job &J, const Ctx &C, uint64_t e, int status, const Att &a, double x) {
+  if (status < 0) raise_flag(C.flags, ZG_FLAG_BUDGET);
+  if (OP == OP_ZIG32) {
+    float r;
+    if (status < 0)
+      r = nan32();
+    else if (a.cls == 0)
+      r = a.neg ? -a.xf : a.xf;
+    else
+      r = (float)(a.neg ? -x : x);
+    ((float *)J.out)[e] = r;
+  } else {
+    const double z = status < 0 ? nan64() : (a.neg ? -x : x);
+    double *out = (double *)J.out;
+    if (OP == OP_MUTATE)
+      out[e] = out[e] + J.sigma * z;
+    else
+      out[e] = z;
+  }
+}
+
+// Where a variate goes after a rejected attempt: its next attempt at draw d2
+// gets its fast test now; fast -> done, else it is queued (wedge) or listed
+// (tail) with draw d2.
+template <int OP, int KIND>
+DEV void next_attempt(const Job &J, const Ctx &C, uint64_t e, uint32_t s, uint64_t v, uint32_t d2,
+                      uint32_t off, bool &to_q, bool &to_t, uint32_t &ent) {
+  if (d2 >= C.dmax) {
+    Att none{};
+    finish<OP>(J, C, e, -1, none, 0.0);
+    return;
+  }
+  const Att a = decode_attempt<OP, KIND>(C, J.seed, s, v, d2);
+  if (a.cls == 0) {
+    finish<OP>(J, C, e, 1, a, a.x);
+  } else {
+    ent = qent(off, d2, 0);
+    to_q = a.cls == 1;
+    to_t = a.cls == 2;
+  }
+}
+
+// One round over up to 64 main-queue entries: wedge steps.
+template <int OP, int KIND>
+DEV void wedge_round(const Job &J, const Ctx &C, Queues &Q, uint64_t e_base) {
   const uint32_t lane = lane_id();
-  if (qn > keep) __threadfence_block();   // placeholders are written before any patch
-  while (qn > keep) {
-    const uint32_t m = qn < 64 ? qn : 64;
+  const uint32_t m = Q.qn < 64 ? Q.qn : 64;
+  const bool has = lane < m;
+  const uint32_t ent = has ? Q.q[Q.qn - m + lane] : 0u;
+  Q.qn = uni(Q.qn - m);
+  __builtin_amdgcn_wave_barrier();
+  bool to_q = false, to_t = false;
+  uint32_t nent = 0;
+  if (has) {
+    const uint32_t off = ent & OFF_MASK;
+    const uint32_t d = (ent >> 21) & 255u;
+    const uint64_t e = e_base + off;
+    uint32_t s;
+    uint64_t v;
+    split(J, e, s, v);
+    const Att a = d < C.dmax ? decode_attempt<OP, KIND>(C, J.seed, s, v, d) : Att{};
+    if (d >= C.dmax) {
+      finish<OP>(J, C, e, -1, a, 0.0);
+    } else if (a.cls == 0) {
+      finish<OP>(J, C, e, 1, a, a.x);
+    } else if (a.cls == 2) {
+      to_t = true;   // defer the tail step
+      nent = qent(off, d, 0);
+    } else if (d + 1 >= C.dmax) {
+      finish<OP>(J, C, e, -1, a, 0.0);
+    } else {
+      const double u = u53(wordk<KIND>(C.T, J.seed, s, v, d + 1));
+      const double y = C.T->y[a.i - 1] + u * C.T->dy[a.i];
+      if (y < exp(-0.5 * (a.x * a.x)))
+        finish<OP>(J, C, e, 1, a, a.x);
+      else
+        next_attempt<OP, KIND>(J, C, e, s, v, d + 2, off, to_q, to_t, nent);
+    }
+  }
+  qpush2(Q.q, Q.qn, to_q, nent, false, 0u);
+  qpush2(Q.t, Q.tn, to_t, nent, false, 0u);
+}
+
+// One round over up to 64 tail-list entries: tail steps.
+template <int OP, int KIND>
+DEV void tail_round(const Job &J, const Ctx &C, Queues &Q, uint64_t e_base) {
+  const uint32_t lane = lane_id();
+  const uint32_t m = Q.tn < 64 ? Q.tn : 64;
+  const bool has = lane < m;
+  const uint32_t ent = has ? Q.t[Q.tn - m + lane] : 0u;
+  Q.tn = uni(Q.tn - m);
+  __builtin_amdgcn_wave_barrier();
+  bool to_q = false, to_t = false;
+  uint32_t nent = 0;
+  if (has) {
+    const uint32_t off = ent & OFF_MASK;
+    const uint32_t d = (ent >> 21) & 255u;
+    const uint64_t e = e_base + off;
+    uint32_t s;
+    uint64_t v;
+    split(J, e, s, v);
+    Att a = decode_attempt<OP, KIND>(C, J.seed, s, v, d);   // sign of the attempt
+    if (d + 2 >= C.dmax) {
+      finish<OP>(J, C, e, -1, a, 0.0);
+    } else {
+      const double u1 = u53p(wordk<KIND>(C.T, J.seed, s, v, d + 1));
+      const double u2 = u53(wordk<KIND>(C.T, J.seed, s, v, d + 2));
+      const double r = C.T->r;
+      const double t = -log(u1) / r;
+      if (u2 < exp(-0.5 * (t * t))) {
+        a.cls = 2;
+        finish<OP>(J, C, e, 1, a, r + t);
+      } else {
+        next_attempt<OP, KIND>(J, C, e, s, v, d + 3, off, to_q, to_t, nent);
+      }
+    }
+  }
+  qpush2(Q.q, Q.qn, to_q, nent, false, 0u);
+  qpush2(Q.t, Q.tn, to_t, nent, false, 0u);
+}
+
+// Drains the main queue down to `keep` entries (full rounds); the tail list
+// is run when it could overflow, or completely when `final`.  Rounds end:
+// every requeue advances a variate's draw index by at least 2.
+template <int OP, int KIND>
+DEV void drain(const Job &J, const Ctx &C, Queues &Q, uint32_t keep, bool final,
+               uint64_t e_base) {
+  if (Q.qn > keep || (final && Q.tn > 0) || Q.tn > TCAP - 64)
+    __threadfence_block();   // placeholders are written before any patch
+  for (;;) {
+    while (Q.qn > keep) {
+      wedge_round<OP, KIND>(J, C, Q, e_base);
+      if (Q.tn > TCAP - 64) tail_round<OP, KIND>(J, C, Q, e_base);
+    }
+    if (!final || Q.tn == 0) break;
+    tail_round<OP, KIND>(J, C, Q, e_base);
+  }
+}
+
+// Polar drain: one attempt per round, rejected pairs requeued.
+template <int KIND>
+DEV void drain_polar(const Job &J, const Ctx &C, Queues &Q, uint32_t keep, uint64_t e_base) {
+  const uint32_t lane = lane_id();
+  if (Q.qn > keep) __threadfence_block();
+  while (Q.qn > keep) {
+    const uint32_t m = Q.qn < 64 ? Q.qn : 64;
     const bool has = lane < m;
-    const uint64_t ent = has ? q[qn - m + lane] : 0;
-    qn = uni(qn - m);
+    const uint32_t ent = has ? Q.q[Q.qn - m + lane] : 0u;
+    Q.qn = uni(Q.qn - m);
     __builtin_amdgcn_wave_barrier();
+    bool pend = false;
+    uint32_t requeue = 0;
     if (has) {
-      const uint64_t v = ent & E_MASK;
-      const uint32_t s = (uint32_t)(ent >> 40) & 0xFFFFu;
-      uint32_t d = (uint32_t)(ent >> 56);
-      const uint64_t e = (uint64_t)(s - J.s0) * J.n_per + (v - J.first);
-      if (OP == OP_ZIG64 || OP == OP_MUTATE) {
-        Step st;
-        for (;;) {
-          st = attempt64<KIND>(C.T, C.f64, J.seed, s, v, d, C.dmax);
-          if (st.status != 0) break;
-          d = st.next_d;
-        }
-        double z = st.status == 1 ? st.x : nan64();
-        if (st.status < 0) raise_flag(C.flags, ZG_FLAG_BUDGET);
-        double *out = (double *)J.out;
-        if (OP == OP_MUTATE)
-          out[e] = out[e] + J.sigma * z;
-        else
-          out[e] = z;
-      } else if (OP == OP_ZIG32) {
-        Step32 st;
-        for (;;) {
-          st = attempt32<KIND>(C.T, C.f32, J.seed, s, v, d, C.dmax);
-          if (st.status != 0) break;
-          d = st.next_d;
-        }
-        if (st.status < 0) raise_flag(C.flags, ZG_FLAG_BUDGET);
-        ((float *)J.out)[e] = st.status == 1 ? st.x : nan32();
-      } else {  // OP_POLAR
-        const bool pair = d & 1;
-        d &= ~1u;
-        const uint64_t p = v >> 1;
-        PolarStep st;
-        for (;;) {
-          st = polar_attempt<KIND>(C.T, J.seed, s, p, d, C.dmax);
-          if (st.status != 0) break;
-          d = st.next_d;
-        }
+      const uint32_t off = ent & OFF_MASK;
+      const uint32_t d = (ent >> 21) & 255u;
+      const uint32_t fl = ent >> 29;
+      const uint64_t e = e_base + off;
+      uint32_t s;
+      uint64_t v;
+      split(J, e, s, v);
+      PolarStep st = polar_attempt<KIND>(C.T, J.seed, s, v >> 1, d, C.dmax);
+      if (st.status == 0) {
+        pend = true;
+        requeue = qent(off, st.next_d, fl);
+      } else {
         if (st.status < 0) {
           raise_flag(C.flags, ZG_FLAG_BUDGET);
           st.z1 = st.z2 = nan64();
         }
         double *out = (double *)J.out;
-        if (pair) {
+        if (fl & F_PAIR) {
           out[e] = st.z1;
           out[e + 1] = st.z2;
         } else {
@@ -321,8 +531,36 @@ DEV void drain(const Job &J, const Ctx &C, uint64_t *q, uint32_t &qn, uint32_t k
         }
       }
     }
-    __builtin_amdgcn_wave_barrier();
+    qpush2(Q.q, Q.qn, pend, requeue, false, 0u);
   }
+}
+
+// Flushes a lane's slow-element bits (bit b = element OFFS[b & 3] + (b >> 2)
+// steps after the lane's group base) into the main queue: a wave-wide
+// exclusive prefix of the popcounts from five ballots, then each lane writes
+// its entries.  Wave-uniform call.
+template <uint32_t STEP, uint32_t CH, bool PAIRS>
+DEV void flush_bits(Queues &Q, uint32_t bits, uint32_t lane_base) {
+  const uint32_t p = __builtin_popcount(bits);   // 0..16
+  const uint64_t B0 = __builtin_amdgcn_ballot_w64((p & 1) != 0);
+  const uint64_t B1 = __builtin_amdgcn_ballot_w64((p & 2) != 0);
+  const uint64_t B2 = __builtin_amdgcn_ballot_w64((p & 4) != 0);
+  const uint64_t B3 = __builtin_amdgcn_ballot_w64((p & 8) != 0);
+  const uint64_t B4 = __builtin_amdgcn_ballot_w64((p & 16) != 0);
+  if ((B0 | B1 | B2 | B3 | B4) == 0) return;
+  uint32_t pos = Q.qn + prefix_below(B0) + 2 * prefix_below(B1) + 4 * prefix_below(B2) +
+                 8 * prefix_below(B3) + 16 * prefix_below(B4);
+  while (bits) {
+    const uint32_t b = __builtin_ctz(bits);
+    bits &= bits - 1;
+    const uint32_t t = b & 3;
+    const uint32_t o = PAIRS ? ((t >> 1) * CH + (t & 1)) : t;
+    Q.q[pos++] = lane_base + (b >> 2) * STEP + o;
+  }
+  Q.qn = uni(Q.qn + (uint32_t)__popcll(B0) + 2 * (uint32_t)__popcll(B1) +
+             4 * (uint32_t)__popcll(B2) + 8 * (uint32_t)__popcll(B3) +
+             16 * (uint32_t)__popcll(B4));
+  __builtin_amdgcn_wave_barrier();
 }
 
 // --------------------------------------------------------- lane constants
@@ -375,194 +613,254 @@ DEV double fast64(const Fast64 *tab, uint64_t W, bool &fast) {
   const Fast64 f = tab[hi >> 25];
   const uint64_t j = (W >> 3) & MASK53;
   fast = j < f.k;
-  return flip_hi((double)j * f.w, hi);
+  return flip_hi(to_f64(j) * f.w, hi);
+}
+
+// Per-tile loop state of the ziggurat kernels.
+struct TileState {
+  uint64_t k, r;        // stream position of the step (wave-uniform)
+  uint32_t bits, sub;   // slow-element bits of the current group, step in group
+  uint32_t lane_base;   // queue offset of the lane's first element in the group
+};
+
+// One ziggurat step: 4 elements per lane.  FULL: the whole step lies inside
+// the tile (no masks).  Returns the lane's 4 slow bits.
+template <int OP, int KIND, bool FULL>
+DEV uint32_t zig_step(const Job &J, const Ctx &C, const LaneConst &LC, uint64_t ec, uint64_t e_end,
+                      uint32_t s, uint64_t vc) {
+  constexpr uint32_t E = (OP == OP_ZIG32) ? 4 : 2;
+  constexpr uint32_t CH = 64 * E;
+  constexpr bool LCG = KIND == ZG_JAVA_LCG48;
+  const uint32_t lane = lane_id();
+  const uint64_t e0 = ec + (uint64_t)E * lane;
+  const uint64_t seed = J.seed;
+  uint32_t b4 = 0;
+  if (OP == OP_ZIG64 || OP == OP_MUTATE) {
+    uint64_t W[4];
+    if (LCG) {
+      uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
+      W[0] = lcg_word_from(aff(LC.a[0], Sc));
+      W[1] = lcg_word_from(aff(LC.a[1], Sc));
+      Sc = aff(C.T->lcg.jump[1][1], Sc);   // 256 steps = the next 128-element chunk
+      W[2] = lcg_word_from(aff(LC.a[0], Sc));
+      W[3] = lcg_word_from(aff(LC.a[1], Sc));
+    } else {
+      const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + vc);
+      W[0] = mix64(zc + LC.g[0]);
+      W[1] = mix64(zc + LC.g[1]);
+      W[2] = mix64(zc + GAMMA * (uint64_t)CH + LC.g[0]);
+      W[3] = mix64(zc + GAMMA * (uint64_t)CH + LC.g[1]);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      const uint64_t ea = e0 + u * CH;
+      const bool ok0 = FULL || ea < e_end, ok1 = FULL || ea + 1 < e_end;
+      bool fast0, fast1;
+      double x0 = fast64(C.f64, W[2 * u], fast0);
+      double x1 = fast64(C.f64, W[2 * u + 1], fast1);
+      double *out = (double *)J.out + ea;
+      if (OP == OP_MUTATE) {
+        if (FULL || (ok0 && ok1)) {
+          const double2 old = *(const double2 *)out;
+          x0 = fast0 ? old.x + J.sigma * x0 : old.x;
+          x1 = fast1 ? old.y + J.sigma * x1 : old.y;
+        } else if (ok0) {
+          const double old = out[0];
+          x0 = fast0 ? old + J.sigma * x0 : old;
+        }
+      }
+      if (FULL || (ok0 && ok1)) {
+        *(double2 *)out = make_double2(x0, x1);
+      } else if (ok0) {
+        out[0] = x0;
+      }
+      b4 |= ((ok0 && !fast0) ? 1u : 0u) << (2 * u);
+      b4 |= ((ok1 && !fast1) ? 2u : 0u) << (2 * u);
+    }
+  } else {  // OP_ZIG32
+    uint32_t uw[4];
+    if (!LCG) {
+      const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + (vc >> 1));
+      const uint64_t Wa = mix64(zc + LC.g[0]), Wb = mix64(zc + LC.g[1]);
+      if ((vc & 1) == 0) {
+        uw[0] = (uint32_t)(Wa >> 32);
+        uw[1] = (uint32_t)Wa;
+        uw[2] = (uint32_t)(Wb >> 32);
+        uw[3] = (uint32_t)Wb;
+      } else {
+        const uint64_t Wc = mix64(zc + LC.g[2]);
+        uw[0] = (uint32_t)Wa;
+        uw[1] = (uint32_t)(Wb >> 32);
+        uw[2] = (uint32_t)Wb;
+        uw[3] = (uint32_t)(Wc >> 32);
+      }
+    } else {
+      const uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) uw[t] = (uint32_t)(lcg_word_from(aff(LC.a[t], Sc)) >> 32);
+    }
+    float x[4];
+    bool ok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const Fast32 f = C.f32[uw[t] >> 25];
+      const uint32_t j = uw[t] & 0xFFFFFFu;
+      ok[t] = FULL || e0 + t < e_end;
+      const float xf = (float)j * f.w;
+      x[t] = __int_as_float(__float_as_int(xf) ^ (int)((uw[t] << 7) & 0x80000000u));
+      b4 |= ((ok[t] && !(j < f.k)) ? 1u : 0u) << t;
+    }
+    float *out = (float *)J.out + e0;
+    if (FULL || ok[3]) {
+      *(float4 *)out = make_float4(x[0], x[1], x[2], x[3]);   // slow ones: placeholders
+    } else {
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (ok[t]) out[t] = x[t];
+    }
+  }
+  return b4;
+}
+
+// One polar step: a pair per lane (2 elements).
+template <int KIND>
+DEV void polar_step(const Job &J, const Ctx &C, const LaneConst &LC, Queues &Q, uint64_t ec,
+                    uint64_t e_end, uint32_t s, uint64_t vc, bool clean, uint32_t o0) {
+  constexpr bool LCG = KIND == ZG_JAVA_LCG48;
+  const uint32_t lane = lane_id();
+  const uint64_t e0 = ec + 2ull * lane;
+  const bool ok0 = e0 < e_end, ok1 = e0 + 1 < e_end;
+  const bool paired = clean && (vc & 1) == 0 && ok1;   // vc parity is wave-uniform
+  bool push_a, push_b = false;
+  uint32_t ent_a, ent_b = 0;
+  if (paired) {
+    // pair p = vc/2 + lane, attempt 0: draws 0 and 1
+    uint64_t W1, W2;
+    if (LCG) {
+      uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(J.seed), 2 * lcg_index(s, vc >> 1, 0) + 1);
+      uint64_t S1 = aff(LC.a[0], Sc);
+      W1 = lcg_word_from(S1);
+      W2 = lcg_word_from(aff(C.T->lcg.window[1], S1));
+    } else {
+      const uint64_t zc = J.seed + GAMMA * (1ull + ((uint64_t)s << 48) + (vc >> 1));
+      const uint64_t z = zc + LC.g[0];
+      W1 = mix64(z);
+      W2 = mix64(z + (GAMMA << 40));
+    }
+    const PolarStep st = polar_from_words(W1, W2, 0);
+    const bool acc = st.status == 1 && C.dmax >= 2;
+    *(double2 *)((double *)J.out + e0) = make_double2(st.z1, st.z2);   // placeholder if rejected
+    push_a = !acc;
+    ent_a = qent(o0, st.status == 1 ? 0u : 2u, F_PAIR);
+  } else {
+    push_a = ok0;
+    ent_a = qent(o0, 0, 0);
+    push_b = ok1;
+    ent_b = qent(o0 + 1, 0, 0);
+  }
+  qpush2(Q.q, Q.qn, push_a, ent_a, push_b, ent_b);
 }
 
 // Processes elements [e_begin, e_end) of job J with one wave, then drains the
-// wave's queue completely.  e_begin is 16-byte aligned in the output and
+// wave's queues completely.  e_begin is 16-byte aligned in the output and
 // e_end - e_begin is arbitrary.  Elements [0, head) of the job (before the
-// aligned body) are queued first when `with_head`.  Chunks that straddle a
-// stream boundary are queued whole as fresh entries (draw 0): the drain keys
-// each element by itself, so the hot loop never divides.
+// aligned body) are queued first when `with_head`.
+//
+// Ziggurat steps: every lane handles 4 elements per step (two 128-element
+// chunks of FP64 pairs, or one 256-element chunk of FP32 quads), stores all of
+// them with 128-bit stores (a slow element gets a placeholder that the drain
+// overwrites after a fence; for mutation the placeholder is the old value) and
+// records its slow elements in a bit mask that is flushed into the queue every
+// 4 steps.  Steps that straddle a stream boundary mark all their elements slow:
+// the drain keys every element by itself, so the hot loop never divides.
 template <int OP, int KIND>
-DEV void process_tile(const Job &J, const Ctx &C, const LaneConst &LC, uint64_t *q,
+DEV void process_tile(const Job &J, const Ctx &C, const LaneConst &LC, uint32_t *lds,
                       uint64_t e_begin, uint64_t e_end, uint32_t head, bool with_head) {
   constexpr uint32_t E = (OP == OP_ZIG32) ? 4 : 2;
   constexpr uint32_t CH = 64 * E;
   constexpr uint32_t U = (OP == OP_ZIG64 || OP == OP_MUTATE) ? 2 : 1;   // chunks per step
   constexpr uint32_t STEP = CH * U;
-  constexpr bool LCG = KIND == ZG_JAVA_LCG48;
+  constexpr uint32_t GROUP = 4;                                         // steps per flush
+  constexpr bool ZIG = OP != OP_POLAR;
   const uint32_t lane = lane_id();
   e_begin = uni64(e_begin);
   e_end = uni64(e_end);
-  uint32_t qn = 0;
-  if (with_head && head) {
-    uint32_t hs;
-    uint64_t hv;
-    split(J, lane, hs, hv);
-    qpush2(q, qn, lane < head, qentry(hs, hv, 0), false, 0);
-  }
+  // queue offsets are relative to e_base; the head elements precede e_begin
+  const uint64_t e_base = with_head ? 0 : e_begin;
+  Queues Q{lds, lds + QCAP, 0u, 0u};
+  if (with_head && head) qpush2(Q.q, Q.qn, lane < head, qent(lane, 0, 0), false, 0u);
   const bool multi = J.n_streams != 1;
-  uint64_t k = 0, r = e_begin;
+  TileState S;
+  S.k = 0;
+  S.r = e_begin;
   if (multi) {
-    k = uni64(e_begin / J.n_per);
-    r = uni64(e_begin - k * J.n_per);
+    S.k = uni64(e_begin / J.n_per);
+    S.r = uni64(e_begin - S.k * J.n_per);
   }
-  const uint64_t seed = J.seed;
+  S.bits = 0;
+  S.sub = 0;
+  S.lane_base = (uint32_t)(e_begin - e_base) + E * lane;
   for (uint64_t ec = e_begin; ec < e_end; ec += STEP) {
-    const bool clean = !multi || r + STEP <= J.n_per;
-    const uint32_t s = uni(J.s0 + (uint32_t)k);
-    const uint64_t vc = uni64(J.first + r);
-    const uint64_t e0 = ec + (uint64_t)E * lane;
-    if (!clean) {
-      // straddles a stream boundary: key every element by itself
+    const bool clean = !multi || S.r + STEP <= J.n_per;
+    const uint32_t s = uni(J.s0 + (uint32_t)S.k);
+    const uint64_t vc = uni64(J.first + S.r);
+    if (ZIG) {
+      uint32_t b4;
+      if (!clean) {
+        // straddles a stream boundary: every element goes to the drain
+        const uint64_t e0 = ec + (uint64_t)E * lane;
+        b4 = 0;
 #pragma unroll
-      for (uint32_t u = 0; u < U; ++u)
-#pragma unroll
-        for (uint32_t t = 0; t < E; t += 2) {
-          const uint64_t ea = e0 + u * CH + t, eb = ea + 1;
-          uint32_t sa, sb;
-          uint64_t va, vb;
-          split(J, ea, sa, va);
-          split(J, eb, sb, vb);
-          qpush2(q, qn, ea < e_end, qentry(sa, va, 0), eb < e_end, qentry(sb, vb, 0));
+        for (uint32_t t = 0; t < 4; ++t) {
+          const uint64_t et = e0 + (U == 2 ? (t >> 1) * CH + (t & 1) : t);
+          b4 |= (et < e_end ? 1u : 0u) << t;
         }
-    } else if (OP == OP_ZIG64 || OP == OP_MUTATE) {
-      uint64_t W[2 * U];
-      if (LCG) {
-        uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-          W[2 * u] = lcg_word_from(aff(LC.a[0], Sc));
-          W[2 * u + 1] = lcg_word_from(aff(LC.a[1], Sc));
-          Sc = aff(C.T->lcg.jump[1][1], Sc);   // 256 steps = the next 128-element chunk
-        }
+      } else if (ec + STEP <= e_end) {
+        b4 = zig_step<OP, KIND, true>(J, C, LC, ec, e_end, s, vc);
       } else {
-        const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + vc);
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-          W[2 * u] = mix64(zc + GAMMA * (uint64_t)(u * CH) + LC.g[0]);
-          W[2 * u + 1] = mix64(zc + GAMMA * (uint64_t)(u * CH) + LC.g[1]);
-        }
+        b4 = zig_step<OP, KIND, false>(J, C, LC, ec, e_end, s, vc);
       }
-      const bool full = ec + STEP <= e_end;   // wave-uniform: no tail masks needed
-#pragma unroll
-      for (uint32_t u = 0; u < U; ++u) {
-        const uint64_t ea = e0 + u * CH;
-        const bool ok0 = full || ea < e_end, ok1 = full || ea + 1 < e_end;
-        bool fast0, fast1;
-        double x0 = fast64(C.f64, W[2 * u], fast0);
-        double x1 = fast64(C.f64, W[2 * u + 1], fast1);
-        double *out = (double *)J.out + ea;
-        // Every lane stores its whole pair: a slow element gets a placeholder
-        // (the old value for mutation, so the drain can still read it) that
-        // the drain overwrites after a fence.
-        if (OP == OP_MUTATE) {
-          if (ok0 && ok1) {
-            double2 old = *(const double2 *)out;
-            x0 = fast0 ? old.x + J.sigma * x0 : old.x;
-            x1 = fast1 ? old.y + J.sigma * x1 : old.y;
-          } else if (ok0) {
-            double old = out[0];
-            x0 = fast0 ? old + J.sigma * x0 : old;
-          }
-        }
-        if (ok0 && ok1) {
-          *(double2 *)out = make_double2(x0, x1);
-        } else if (ok0) {
-          out[0] = x0;
-        }
-        const uint64_t va = vc + u * CH + 2 * lane;
-        qpush2(q, qn, ok0 && !fast0, qentry(s, va, 0), ok1 && !fast1, qentry(s, va + 1, 0));
+      S.bits |= b4 << (4 * S.sub);
+      if (++S.sub == GROUP) {
+#ifndef NO_FLUSH
+        flush_bits<STEP, CH, U == 2>(Q, S.bits, S.lane_base);
+#else
+        if (S.bits == 0x12345678u) Q.q[0] = 1;
+#endif
+        S.bits = 0;
+        S.sub = 0;
+        S.lane_base += GROUP * STEP;
+#ifndef NO_DRAIN
+        if (Q.qn > (uint32_t)QCAP - GROUP * STEP) drain<OP, KIND>(J, C, Q, 63, false, e_base);
+#else
+        Q.qn = 0;
+#endif
       }
-    } else if (OP == OP_ZIG32) {
-      uint32_t uw[4];
-      if (!LCG) {
-        const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + (vc >> 1));
-        const uint64_t Wa = mix64(zc + LC.g[0]), Wb = mix64(zc + LC.g[1]);
-        if ((vc & 1) == 0) {
-          uw[0] = (uint32_t)(Wa >> 32);
-          uw[1] = (uint32_t)Wa;
-          uw[2] = (uint32_t)(Wb >> 32);
-          uw[3] = (uint32_t)Wb;
-        } else {
-          const uint64_t Wc = mix64(zc + LC.g[2]);
-          uw[0] = (uint32_t)Wa;
-          uw[1] = (uint32_t)(Wb >> 32);
-          uw[2] = (uint32_t)Wb;
-          uw[3] = (uint32_t)(Wc >> 32);
-        }
-      } else {
-        const uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) uw[t] = (uint32_t)(lcg_word_from(aff(LC.a[t], Sc)) >> 32);
+    } else {
+      polar_step<KIND>(J, C, LC, Q, ec, e_end, s, vc, clean, S.lane_base + S.sub * STEP);
+      if (++S.sub == GROUP) {
+        S.sub = 0;
+        S.lane_base += GROUP * STEP;
       }
-      float x[4];
-      bool fast[4], ok[4];
-      const bool full = ec + STEP <= e_end;   // wave-uniform: no tail masks needed
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const Fast32 f = C.f32[uw[t] >> 25];
-        const uint32_t j = uw[t] & 0xFFFFFFu;
-        fast[t] = j < f.k;
-        ok[t] = full || e0 + t < e_end;
-        const float xf = (float)j * f.w;
-        x[t] = __int_as_float(__float_as_int(xf) ^ (int)((uw[t] << 7) & 0x80000000u));
-      }
-      float *out = (float *)J.out + e0;
-      if (ok[3]) {
-        *(float4 *)out = make_float4(x[0], x[1], x[2], x[3]);   // slow ones: placeholders
-      } else {
-#pragma unroll
-        for (int t = 0; t < 3; ++t)
-          if (ok[t]) out[t] = x[t];
-      }
-      const uint64_t va = vc + 4 * lane;
-      qpush2(q, qn, ok[0] && !fast[0], qentry(s, va, 0), ok[1] && !fast[1], qentry(s, va + 1, 0));
-      qpush2(q, qn, ok[2] && !fast[2], qentry(s, va + 2, 0), ok[3] && !fast[3],
-             qentry(s, va + 3, 0));
-    } else {  // OP_POLAR
-      const bool ok0 = e0 < e_end, ok1 = e0 + 1 < e_end;
-      const bool paired = (vc & 1) == 0 && ok1;   // vc parity is wave-uniform
-      const uint64_t va = vc + 2 * lane;
-      bool push_a, push_b = false;
-      uint64_t ent_a, ent_b = 0;
-      if (paired) {
-        // pair p = vc/2 + lane, attempt 0: draws 0 and 1
-        uint64_t W1, W2;
-        if (LCG) {
-          uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc >> 1, 0) + 1);
-          uint64_t S1 = aff(LC.a[0], Sc);
-          W1 = lcg_word_from(S1);
-          W2 = lcg_word_from(aff(C.T->lcg.window[1], S1));
-        } else {
-          const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + (vc >> 1));
-          const uint64_t z = zc + LC.g[0];
-          W1 = mix64(z);
-          W2 = mix64(z + (GAMMA << 40));
-        }
-        const PolarStep st = polar_from_words(W1, W2, 0);
-        const bool acc = st.status == 1 && C.dmax >= 2;
-        *(double2 *)((double *)J.out + e0) = make_double2(st.z1, st.z2);   // placeholder if rejected
-        push_a = !acc;
-        ent_a = qentry(s, va, (st.status == 1 ? 0u : 2u) | 1u);   // low bit: both elements
-      } else {
-        push_a = ok0;
-        ent_a = qentry(s, va, 0);
-        push_b = ok1;
-        ent_b = qentry(s, va + 1, 0);
-      }
-      qpush2(q, qn, push_a, ent_a, push_b, ent_b);
+      if (Q.qn > (uint32_t)QCAP - STEP) drain_polar<KIND>(J, C, Q, 63, e_base);
     }
-    if (qn > (uint32_t)(QCAP - STEP)) drain<OP, KIND>(J, C, q, qn, 63);
-    r += STEP;
+    S.r += STEP;
     if (multi)
-      while (r >= J.n_per) {
-        r -= J.n_per;
-        ++k;
+      while (S.r >= J.n_per) {
+        S.r -= J.n_per;
+        ++S.k;
       }
   }
-  drain<OP, KIND>(J, C, q, qn, 0);
+  if (ZIG) {
+#ifndef NO_FLUSH
+    if (S.sub) flush_bits<STEP, CH, U == 2>(Q, S.bits, S.lane_base);
+#endif
+#ifndef NO_DRAIN
+    drain<OP, KIND>(J, C, Q, 0, true, e_base);
+#endif
+  } else {
+    drain_polar<KIND>(J, C, Q, 0, e_base);
+  }
 }
 
 // Loads the fast tables into LDS (whole block; ends with a barrier).
@@ -583,7 +881,7 @@ __global__ __launch_bounds__(1024) void k_fill(Job J, const DevTables *__restric
                                                uint32_t head) {
   __shared__ Fast64 s_f64[ZG_LAYERS];
   __shared__ Fast32 s_f32[ZG_LAYERS];
-  extern __shared__ uint64_t s_q[];   // waves x QCAP
+  extern __shared__ uint32_t s_q[];   // waves x (QCAP + TCAP)
   load_fast(T, s_f64, s_f32, OP != OP_ZIG32, OP == OP_ZIG32);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
@@ -593,7 +891,7 @@ __global__ __launch_bounds__(1024) void k_fill(Job J, const DevTables *__restric
     LaneConst LC = lane_constants<OP, KIND>(T);
     uint64_t e_end = b + tile < J.n_total ? b + tile : J.n_total;
     uint64_t e_begin = b < e_end ? b : e_end;
-    process_tile<OP, KIND>(J, C, LC, s_q + wave * QCAP, e_begin, e_end, head, gw == 0);
+    process_tile<OP, KIND>(J, C, LC, s_q + wave * (QCAP + TCAP), e_begin, e_end, head, gw == 0);
   }
 }
 
@@ -671,7 +969,7 @@ __global__ __launch_bounds__(512) void k_batch(DevRequest *R, const BatchHeader 
                                                 uint32_t *flags) {
   __shared__ Fast64 s_f64[ZG_LAYERS];
   __shared__ Fast32 s_f32[ZG_LAYERS];
-  extern __shared__ uint64_t s_q[];   // waves x QCAP
+  extern __shared__ uint32_t s_q[];   // waves x (QCAP + TCAP)
   load_fast(T, s_f64, s_f32, true, true);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
@@ -702,11 +1000,11 @@ __global__ __launch_bounds__(512) void k_batch(DevRequest *R, const BatchHeader 
   case OPV: {                                                                              \
     if (J.kind == ZG_JAVA_LCG48) {                                                         \
       LaneConst LC = lane_constants<OPV, ZG_JAVA_LCG48>(T);                                \
-      process_tile<OPV, ZG_JAVA_LCG48>(J, C, LC, s_q + wave * QCAP, e_begin, e_end, rq.head, \
+      process_tile<OPV, ZG_JAVA_LCG48>(J, C, LC, s_q + wave * (QCAP + TCAP), e_begin, e_end, rq.head, \
                                        lt == 0);                                           \
     } else {                                                                               \
       LaneConst LC = lane_constants<OPV, ZG_SPLITMIX64>(T);                                \
-      process_tile<OPV, ZG_SPLITMIX64>(J, C, LC, s_q + wave * QCAP, e_begin, e_end, rq.head, \
+      process_tile<OPV, ZG_SPLITMIX64>(J, C, LC, s_q + wave * (QCAP + TCAP), e_begin, e_end, rq.head, \
                                        lt == 0);                                           \
     }                                                                                      \
   } break;
@@ -743,7 +1041,8 @@ static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax
   if (tiles == 0) tiles = 1;   // head-only jobs still need wave 0
   uint64_t blocks = (tiles + waves - 1) / waves;
   hipLaunchKernelGGL((k_fill<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * waves),
-                     (size_t)waves * QCAP * sizeof(uint64_t), stream, J, T, dmax, flags, tile, head);
+                     (size_t)waves * (QCAP + TCAP) * sizeof(uint32_t), stream, J, T, dmax, flags,
+                     tile, head);
   return hipGetLastError();
 }
 
@@ -784,6 +1083,6 @@ hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, 
 
 const void *kernel_reserve() { return (const void *)k_reserve; }
 const void *kernel_batch() { return (const void *)k_batch; }
-size_t batch_lds_bytes(uint32_t waves) { return (size_t)waves * QCAP * sizeof(uint64_t); }
+size_t batch_lds_bytes(uint32_t waves) { return (size_t)waves * (QCAP + TCAP) * sizeof(uint32_t); }
 
 }  // namespace zg
