@@ -163,7 +163,7 @@ def main():
     wall_ms = wall * 1e3 / args.steps
     bytes_per = 8.0 * n
     achieved = bytes_per / (ms * 1e-3) / 1e9
-    kernel = "k_fill<OP_ZIG64>" if main_key == "zig" else "k_fill<OP_POLAR>"
+    kernel = "k_zig<OP_ZIG64>" if main_key == "zig" else "k_fill<OP_POLAR>"
     traffic = read_traffic(kernel)
     line = {
         "metric": METRIC,

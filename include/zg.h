@@ -239,12 +239,15 @@ zg_status zg_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, uint64_t 
 
 /* Launch shape of the generation kernels: elements per wave tile (f64 units;
  * multiple of 128), waves per workgroup (1..16), persistent workgroups per CU
- * for the batch kernel.  Any shape gives the same bits. */
+ * for the batch kernel, and queue_cap: the workgroup's slow-path queue
+ * capacity of the plain ziggurat fills (0 = the built-in maximum of 2048;
+ * smaller values only serve to exercise the overflow path).  Any shape gives
+ * the same bits. */
 typedef struct zg_tune {
   uint32_t tile;
   uint32_t waves_per_block;
   uint32_t batch_blocks_per_cu;
-  uint32_t reserved;
+  uint32_t queue_cap;
 } zg_tune;
 #define ZG_TUNE_FILL_F64 0
 #define ZG_TUNE_FILL_F32 1

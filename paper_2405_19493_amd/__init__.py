@@ -89,7 +89,7 @@ class Request(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
-                ("batch_blocks_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("batch_blocks_per_cu", ctypes.c_uint32), ("queue_cap", ctypes.c_uint32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -349,10 +349,10 @@ class Context:
     def zg_get_tune(self, cls):
         t = Tune()
         self._c(lib.zg_get_tune(self.h, cls, ctypes.byref(t)), "zg_get_tune")
-        return (t.tile, t.waves_per_block, t.batch_blocks_per_cu)
+        return (t.tile, t.waves_per_block, t.batch_blocks_per_cu, t.queue_cap)
 
-    def zg_set_tune(self, cls, tile, waves_per_block, batch_blocks_per_cu=2):
-        t = Tune(tile, waves_per_block, batch_blocks_per_cu, 0)
+    def zg_set_tune(self, cls, tile, waves_per_block, batch_blocks_per_cu=2, queue_cap=0):
+        t = Tune(tile, waves_per_block, batch_blocks_per_cu, queue_cap)
         self._c(lib.zg_set_tune(self.h, cls, ctypes.byref(t)), "zg_set_tune")
 
     def zg_autotune(self, cache_path=None, nbytes=0, use_cache=True):

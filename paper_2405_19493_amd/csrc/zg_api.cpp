@@ -29,10 +29,10 @@ struct DeviceGuard {
 };
 
 const zg_tune DEFAULT_TUNE[ZG_TUNE_CLASSES] = {
-    {2048, 8, 2, 0},    // FILL_F64
-    {4096, 8, 2, 0},    // FILL_F32
+    {1024, 16, 2, 0},   // FILL_F64
+    {2048, 16, 2, 0},   // FILL_F32
     {2048, 8, 2, 0},    // POLAR
-    {2048, 8, 2, 0},    // MUTATE
+    {1024, 16, 2, 0},   // MUTATE
     {2048, 8, 4, 0},    // BATCH (k_batch is bounded to 512 threads)
 };
 
@@ -97,7 +97,7 @@ zg_status launch_job(zg_ctx *ctx, const Job &J, hipStream_t stream) {
   const zg_tune &t = ctx->tune[tune_class(J.op)];
   uint32_t head = head_of(J.out, J.op, J.n_total);
   hipError_t e = launch_fill(J, ctx->d_tables, ctx->dmax, ctx->d_flags, t.tile, t.waves_per_block,
-                             head, stream);
+                             head, t.queue_cap, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "launch_fill");
   return ZG_OK;
 }
@@ -433,6 +433,7 @@ zg_status zg_set_tune(zg_ctx *ctx, int cls, const zg_tune *in) {
   if (in->waves_per_block < 1 || in->waves_per_block > 16) return ZG_EINVAL;
   if (in->batch_blocks_per_cu < 1 || in->batch_blocks_per_cu > 8) return ZG_EINVAL;
   if (cls == ZG_TUNE_BATCH && (in->tile % 256 || in->waves_per_block > 8)) return ZG_EINVAL;
+  if (in->queue_cap > 2048) return ZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->tune[cls] = *in;
   if (cls == ZG_TUNE_BATCH)

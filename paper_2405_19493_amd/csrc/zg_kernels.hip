@@ -822,19 +822,11 @@ DEV void process_tile(const Job &J, const Ctx &C, const LaneConst &LC, uint32_t 
       }
       S.bits |= b4 << (4 * S.sub);
       if (++S.sub == GROUP) {
-#ifndef NO_FLUSH
         flush_bits<STEP, CH, U == 2>(Q, S.bits, S.lane_base);
-#else
-        if (S.bits == 0x12345678u) Q.q[0] = 1;
-#endif
         S.bits = 0;
         S.sub = 0;
         S.lane_base += GROUP * STEP;
-#ifndef NO_DRAIN
         if (Q.qn > (uint32_t)QCAP - GROUP * STEP) drain<OP, KIND>(J, C, Q, 63, false, e_base);
-#else
-        Q.qn = 0;
-#endif
       }
     } else {
       polar_step<KIND>(J, C, LC, Q, ec, e_end, s, vc, clean, S.lane_base + S.sub * STEP);
@@ -852,12 +844,8 @@ DEV void process_tile(const Job &J, const Ctx &C, const LaneConst &LC, uint32_t 
       }
   }
   if (ZIG) {
-#ifndef NO_FLUSH
     if (S.sub) flush_bits<STEP, CH, U == 2>(Q, S.bits, S.lane_base);
-#endif
-#ifndef NO_DRAIN
     drain<OP, KIND>(J, C, Q, 0, true, e_base);
-#endif
   } else {
     drain_polar<KIND>(J, C, Q, 0, e_base);
   }
@@ -870,6 +858,460 @@ DEV void load_fast(const DevTables *T, Fast64 *f64, Fast32 *f32, bool need64, bo
     if (need32) f32[i] = T->fast32[i];
   }
   __syncthreads();
+}
+
+// ------------------------------------------------ block-pooled ziggurat fill
+//
+// The plain ziggurat fills (FP64, FP32, mutation).  Every wave streams its
+// tile: 256 elements per step, all stored at once with 128-bit stores (an
+// element that failed the fast test gets a placeholder: the rejected
+// candidate, or for mutation the old value).  The slow elements of all waves
+// of the block go into one LDS queue (offsets from the block base).  After one
+// block barrier, which also orders every placeholder store before any patch,
+// the waves drain the pooled queue 64 entries at a time, each lane running the
+// whole attempt loop of one variate and storing its value.  Pooling keeps the
+// drain rounds nearly full: a block tile of 8 x 2048 elements has about 200
+// slow elements, while one wave's tile has about 25.
+//
+// Queue overflow (more slow elements than the queue holds, which hash words
+// practically never produce): a wave whose group of entries does not fit
+// stops queueing, marks the positions it reserved as empty, and after the
+// drain redoes the fast test over the rest of its tile and resolves its own
+// slow elements in-lane.
+
+constexpr uint32_t BSTEP = 256;    // elements per wave step
+constexpr uint32_t BGROUP = 4;     // steps per queue flush
+constexpr uint32_t BQ = 2048;      // block queue capacity (entries)
+constexpr uint32_t QEMPTY = 0xFFFFFFFFu;
+
+// Tables of the fast and slow paths, in LDS.
+struct LdsTabs {
+  Fast64 f64[ZG_LAYERS];
+  Fast32 f32[ZG_LAYERS];
+  double2 yd[ZG_LAYERS];     // (y[i-1], dy[i]) of the wedge test, i >= 1
+  double w24d[ZG_LAYERS];    // FP32 mode: w24 as a double
+};
+
+struct BlockLds {
+  LdsTabs t;
+  uint32_t cnt;
+  uint32_t q[BQ];            // element offsets from the block base
+};
+
+// Loads the tables an op needs (whole block; no barrier).
+template <int OP>
+DEV void load_tabs(const DevTables *T, LdsTabs &L) {
+  for (uint32_t i = threadIdx.x; i < ZG_LAYERS; i += blockDim.x) {
+    if (OP == OP_ZIG32) {
+      L.f32[i] = T->fast32[i];
+      L.w24d[i] = T->w24d[i];
+    } else {
+      L.f64[i] = T->fast64[i];
+    }
+    L.yd[i] = make_double2(i ? T->y[i - 1] : 0.0, T->dy[i]);
+  }
+}
+
+// The whole attempt sequence of one variate from draw 0 (the same steps, in
+// the same order and precision, as attempt64 / attempt32): returns the signed
+// FP64 value, or for FP32 mode the FP32 value widened exactly to double, or
+// the canonical NaN when the draw budget runs out.
+template <int OP, int KIND>
+DEV double resolve(const Job &J, const LdsTabs &L, const DevTables *T, double r, uint32_t dmax,
+                   uint32_t s, uint64_t v, bool &budget) {
+  uint32_t d = 0;
+  double z;
+  for (;;) {
+    if (d >= dmax) {
+      budget = true;
+      z = nan64();
+      break;
+    }
+    uint32_t i, neg;
+    double x;
+    if (OP == OP_ZIG32) {
+      const uint32_t u = word32<KIND>(T, J.seed, s, v, d);
+      i = u >> 25;
+      neg = (u >> 24) & 1;
+      const uint32_t j = u & 0xFFFFFFu;
+      const Fast32 f = L.f32[i];
+      if (j < f.k) {
+        const float xf = (float)j * f.w;
+        z = (double)(neg ? -xf : xf);
+        break;
+      }
+      x = (double)j * L.w24d[i];
+    } else {
+      const uint64_t W = wordk<KIND>(T, J.seed, s, v, d);
+      i = (uint32_t)(W >> 57);
+      neg = (uint32_t)(W >> 56) & 1;
+      const uint64_t j = (W >> 3) & MASK53;
+      const Fast64 f = L.f64[i];
+      x = to_f64(j) * f.w;
+      if (j < f.k) {
+        z = neg ? -x : x;
+        break;
+      }
+    }
+    double thr, arg, xc;
+    uint32_t dn;
+    if (i == 0) {   // tail: x = r + a, a = -log(U1)/r, accept U2 < exp(-a^2/2)
+      if (d + 2 >= dmax) {
+        budget = true;
+        z = nan64();
+        break;
+      }
+      const double u1 = u53p(wordk<KIND>(T, J.seed, s, v, d + 1));
+      thr = u53(wordk<KIND>(T, J.seed, s, v, d + 2));
+      arg = -log(u1) / r;
+      xc = r + arg;
+      dn = d + 3;
+    } else {        // wedge: accept y[i-1] + U dy[i] < exp(-x^2/2)
+      if (d + 1 >= dmax) {
+        budget = true;
+        z = nan64();
+        break;
+      }
+      const double u = u53(wordk<KIND>(T, J.seed, s, v, d + 1));
+      const double2 yd = L.yd[i];
+      thr = yd.x + u * yd.y;
+      arg = x;
+      xc = x;
+      dn = d + 2;
+    }
+    if (thr < exp(-0.5 * (arg * arg))) {
+      z = neg ? -xc : xc;
+      break;
+    }
+    d = dn;
+  }
+  return z;
+}
+
+// Element of slot t (0..3) of a lane in a step starting at ec.
+template <int OP>
+DEV uint64_t slot_elem(uint64_t ec, uint32_t lane, uint32_t t) {
+  if (OP == OP_ZIG32) return ec + 4ull * lane + t;
+  return ec + (t >> 1) * 128ull + 2ull * lane + (t & 1);
+}
+
+// Fast path of one clean step into registers (x: FP64 values, or for mutation
+// old + sigma z with the old value kept where the element is slow; xf: FP32
+// values).  Elements at or beyond e_end are neither computed nor marked.
+// Returns the lane's 4 slow bits.
+template <int OP, int KIND, bool FULL>
+DEV uint32_t step_regs(const Job &J, const Fast64 *f64t, const Fast32 *f32t, const DevTables *T,
+                       const LaneConst &LC, uint64_t ec, uint64_t e_end, uint32_t s, uint64_t vc,
+                       double *x, float *xf) {
+  constexpr bool LCG = KIND == ZG_JAVA_LCG48;
+  const uint32_t lane = lane_id();
+  const uint64_t seed = J.seed;
+  uint32_t b4 = 0;
+  if (OP == OP_ZIG64 || OP == OP_MUTATE) {
+    constexpr uint32_t CH = 128;
+    uint64_t W[4];
+    if (LCG) {
+      uint64_t Sc = lcg_jump(&T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
+      W[0] = lcg_word_from(aff(LC.a[0], Sc));
+      W[1] = lcg_word_from(aff(LC.a[1], Sc));
+      Sc = aff(T->lcg.jump[1][1], Sc);   // 256 steps = the next 128-element chunk
+      W[2] = lcg_word_from(aff(LC.a[0], Sc));
+      W[3] = lcg_word_from(aff(LC.a[1], Sc));
+    } else {
+      const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + vc);
+      W[0] = mix64(zc + LC.g[0]);
+      W[1] = mix64(zc + LC.g[1]);
+      W[2] = mix64(zc + GAMMA * (uint64_t)CH + LC.g[0]);
+      W[3] = mix64(zc + GAMMA * (uint64_t)CH + LC.g[1]);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      const uint64_t ea = ec + u * CH + 2ull * lane;
+      const bool ok0 = FULL || ea < e_end, ok1 = FULL || ea + 1 < e_end;
+      bool fast0, fast1;
+      double x0 = fast64(f64t, W[2 * u], fast0);
+      double x1 = fast64(f64t, W[2 * u + 1], fast1);
+      if (OP == OP_MUTATE) {
+        const double *out = (const double *)J.out + ea;
+        if (FULL || (ok0 && ok1)) {
+          const double2 old = *(const double2 *)out;
+          x0 = fast0 ? old.x + J.sigma * x0 : old.x;
+          x1 = fast1 ? old.y + J.sigma * x1 : old.y;
+        } else if (ok0) {
+          const double old = out[0];
+          x0 = fast0 ? old + J.sigma * x0 : old;
+        }
+      }
+      x[2 * u] = x0;
+      x[2 * u + 1] = x1;
+      b4 |= ((ok0 && !fast0) ? 1u : 0u) << (2 * u);
+      b4 |= ((ok1 && !fast1) ? 2u : 0u) << (2 * u);
+    }
+  } else {  // OP_ZIG32
+    uint32_t uw[4];
+    if (!LCG) {
+      const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + (vc >> 1));
+      const uint64_t Wa = mix64(zc + LC.g[0]), Wb = mix64(zc + LC.g[1]);
+      if ((vc & 1) == 0) {
+        uw[0] = (uint32_t)(Wa >> 32);
+        uw[1] = (uint32_t)Wa;
+        uw[2] = (uint32_t)(Wb >> 32);
+        uw[3] = (uint32_t)Wb;
+      } else {
+        const uint64_t Wc = mix64(zc + LC.g[2]);
+        uw[0] = (uint32_t)Wa;
+        uw[1] = (uint32_t)(Wb >> 32);
+        uw[2] = (uint32_t)Wb;
+        uw[3] = (uint32_t)(Wc >> 32);
+      }
+    } else {
+      const uint64_t Sc = lcg_jump(&T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) uw[t] = (uint32_t)(lcg_word_from(aff(LC.a[t], Sc)) >> 32);
+    }
+    const uint64_t e0 = ec + 4ull * lane;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const Fast32 f = f32t[uw[t] >> 25];
+      const uint32_t j = uw[t] & 0xFFFFFFu;
+      const bool ok = FULL || e0 + t < e_end;
+      const float v = (float)j * f.w;
+      xf[t] = __int_as_float(__float_as_int(v) ^ (int)((uw[t] << 7) & 0x80000000u));
+      b4 |= ((ok && !(j < f.k)) ? 1u : 0u) << t;
+    }
+  }
+  return b4;
+}
+
+// Writes the lane's elements of a step from registers (masked at e_end).
+template <int OP, bool FULL>
+DEV void step_store(const Job &J, uint64_t ec, uint64_t e_end, const double *x, const float *xf) {
+  const uint32_t lane = lane_id();
+  if (OP == OP_ZIG32) {
+    const uint64_t e0 = ec + 4ull * lane;
+    float *out = (float *)J.out + e0;
+    if (FULL || e0 + 3 < e_end) {
+      *(float4 *)out = make_float4(xf[0], xf[1], xf[2], xf[3]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (e0 + t < e_end) out[t] = xf[t];
+    }
+  } else {
+#pragma unroll
+    for (uint32_t u = 0; u < 2; ++u) {
+      const uint64_t ea = ec + u * 128ull + 2ull * lane;
+      double *out = (double *)J.out + ea;
+      if (FULL || ea + 1 < e_end)
+        *(double2 *)out = make_double2(x[2 * u], x[2 * u + 1]);
+      else if (ea < e_end)
+        out[0] = x[2 * u];
+    }
+  }
+}
+
+// Fast path of a step that straddles a stream boundary: every element is
+// keyed by itself (stream and index from its element number).  Same outputs
+// and slow bits as step_regs.
+template <int OP, int KIND>
+DEV uint32_t step_general(const Job &J, const Fast64 *f64t, const Fast32 *f32t,
+                          const DevTables *T, uint64_t ec, uint64_t e_end, double *x, float *xf) {
+  const uint32_t lane = lane_id();
+  uint32_t b4 = 0;
+#pragma unroll
+  for (uint32_t t = 0; t < 4; ++t) {
+    const uint64_t e = slot_elem<OP>(ec, lane, t);
+    if (e < e_end) {
+      uint32_t s;
+      uint64_t v;
+      split(J, e, s, v);
+      bool fast;
+      if (OP == OP_ZIG32) {
+        const uint32_t u = word32<KIND>(T, J.seed, s, v, 0);
+        const Fast32 f = f32t[u >> 25];
+        const uint32_t j = u & 0xFFFFFFu;
+        const float xv = (float)j * f.w;
+        xf[t] = __int_as_float(__float_as_int(xv) ^ (int)((u << 7) & 0x80000000u));
+        fast = j < f.k;
+      } else {
+        x[t] = fast64(f64t, wordk<KIND>(T, J.seed, s, v, 0), fast);
+        if (OP == OP_MUTATE) {
+          const double old = ((const double *)J.out)[e];
+          x[t] = fast ? old + J.sigma * x[t] : old;
+        }
+      }
+      b4 |= (fast ? 0u : 1u) << t;
+    }
+  }
+  return b4;
+}
+
+// Whether the first attempt of variate v of stream s passes the fast test.
+template <int OP, int KIND>
+DEV bool first_fast(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t s, uint64_t v) {
+  if (OP == OP_ZIG32) {
+    const uint32_t u = word32<KIND>(T, J.seed, s, v, 0);
+    return (u & 0xFFFFFFu) < L.f32[u >> 25].k;
+  }
+  const uint64_t W = wordk<KIND>(T, J.seed, s, v, 0);
+  return ((W >> 3) & MASK53) < L.f64[(uint32_t)(W >> 57)].k;
+}
+
+// Stores the resolved value z of element e (the placeholder is overwritten;
+// for mutation the placeholder is the old value).
+template <int OP>
+DEV void patch_store(const Job &J, uint64_t e, double z) {
+  if (OP == OP_ZIG32) {
+    ((float *)J.out)[e] = (float)z;
+  } else {
+    double *out = (double *)J.out;
+    if (OP == OP_MUTATE)
+      out[e] = out[e] + J.sigma * z;
+    else
+      out[e] = z;
+  }
+}
+
+// The steps of a wave's tile [ew, ee): fast path, stores, and the queue
+// flushes every BGROUP steps.  Returns the first element of the group where
+// queueing stopped for lack of space (ee if it never did): that group and the
+// rest of the tile are left to the overflow pass; `stored` is the end of what
+// was stored (final values for fast elements, placeholders for slow ones).
+template <int OP, int KIND>
+DEV uint64_t tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneConst &LC,
+                       uint64_t b0, uint64_t ew, uint64_t ee, uint32_t qcap, uint64_t &stored) {
+  const uint32_t lane = lane_id();
+  const bool multi = J.n_streams != 1;
+  uint32_t s = J.s0;
+  uint64_t rr = ew;
+  if (multi) {
+    uint64_t v;
+    split(J, ew, s, v);
+    s = uni(s);
+    rr = uni64(v - J.first);
+  }
+  uint32_t bits = 0, sub = 0;
+  uint64_t gbase = ew;   // first element of the current group
+  uint64_t stop = ee;
+  for (uint64_t ec = ew; ec < ee; ec += BSTEP) {
+    double x[4];
+    float xf[4];
+    uint32_t b4;
+    const bool full = ec + BSTEP <= ee;
+    if (!multi || rr + BSTEP <= J.n_per) {
+      const uint64_t vc = J.first + rr;
+      if (full)
+        b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ee, s, vc, x, xf);
+      else
+        b4 = step_regs<OP, KIND, false>(J, L.t.f64, L.t.f32, T, LC, ec, ee, s, vc, x, xf);
+    } else {
+      b4 = step_general<OP, KIND>(J, L.t.f64, L.t.f32, T, ec, ee, x, xf);
+    }
+    if (full)
+      step_store<OP, true>(J, ec, ee, x, xf);
+    else
+      step_store<OP, false>(J, ec, ee, x, xf);
+    {
+      bits |= b4 << (4 * sub);
+      if (++sub == BGROUP || !full || ec + BSTEP >= ee) {
+        // a wave-wide exclusive prefix of the slow counts (0..16 per lane)
+        const uint32_t c = __builtin_popcount(bits);
+        const uint64_t B0 = __builtin_amdgcn_ballot_w64((c & 1) != 0);
+        const uint64_t B1 = __builtin_amdgcn_ballot_w64((c & 2) != 0);
+        const uint64_t B2 = __builtin_amdgcn_ballot_w64((c & 4) != 0);
+        const uint64_t B3 = __builtin_amdgcn_ballot_w64((c & 8) != 0);
+        const uint64_t B4 = __builtin_amdgcn_ballot_w64((c & 16) != 0);
+        const uint32_t tot = (uint32_t)__popcll(B0) + 2 * (uint32_t)__popcll(B1) +
+                             4 * (uint32_t)__popcll(B2) + 8 * (uint32_t)__popcll(B3) +
+                             16 * (uint32_t)__popcll(B4);
+        if (tot) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&L.cnt, tot);
+          base = uni(base);
+          if (base + tot <= qcap) {
+            uint32_t p = base + prefix_below(B0) + 2 * prefix_below(B1) +
+                         4 * prefix_below(B2) + 8 * prefix_below(B3) + 16 * prefix_below(B4);
+            while (bits) {
+              const uint32_t b = __builtin_ctz(bits);
+              bits &= bits - 1;
+              L.q[p++] = (uint32_t)(slot_elem<OP>(gbase + (b >> 2) * BSTEP, lane, b & 3) - b0);
+            }
+          } else {
+            // does not fit: mark the reserved positions below qcap empty and
+            // leave this group and the rest of the tile to the overflow pass
+            for (uint32_t p = base + lane; p < base + tot && p < qcap; p += 64) L.q[p] = QEMPTY;
+            stop = gbase;
+            stored = full ? ec + BSTEP : ee;
+            break;
+          }
+        }
+        bits = 0;
+        sub = 0;
+        gbase = ec + BSTEP;
+      }
+    }
+    rr += BSTEP;
+    if (multi)
+      while (rr >= J.n_per) {
+        rr -= J.n_per;
+        ++s;
+      }
+  }
+  return stop;
+}
+
+template <int OP, int KIND>
+__global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict__ T,
+                                              uint32_t dmax, uint32_t *flags, uint32_t tile,
+                                              uint32_t head, uint32_t qcap) {
+  __shared__ BlockLds L;
+  load_tabs<OP>(T, L.t);
+  if (threadIdx.x == 0) L.cnt = 0;
+  __syncthreads();
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const uint32_t lane = lane_id();
+  const double r = T->r;
+  bool budget = false;
+  const uint64_t bt = (uint64_t)tile * nw;
+  const uint64_t b0 = uni64((uint64_t)blockIdx.x * bt + head);
+  const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
+  const uint64_t ew = uni64(b0 + (uint64_t)wave * tile < b1 ? b0 + (uint64_t)wave * tile : b1);
+  const uint64_t ee = uni64(ew + tile < b1 ? ew + tile : b1);
+  const LaneConst LC = lane_constants<OP, KIND>(T);
+  uint64_t stop = ee, stored = ee;
+  if (ew < ee) stop = tile_pass<OP, KIND>(J, L, T, LC, b0, ew, ee, qcap, stored);
+  __syncthreads();   // placeholders before patches; the queue is complete
+  const uint32_t n = uni(L.cnt < qcap ? L.cnt : qcap);
+  for (uint32_t cb = wave * 64; cb < n; cb += nw * 64) {
+    const uint32_t p = cb + lane;
+    const uint32_t ent = p < n ? L.q[p] : QEMPTY;
+    if (ent != QEMPTY) {
+      const uint64_t e = b0 + ent;
+      uint32_t se;
+      uint64_t ve;
+      split(J, e, se, ve);
+      patch_store<OP>(J, e, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
+    }
+  }
+  // overflow pass: the elements of [stop, ee) that are not final yet, each
+  // from its first draw (the barrier above orders the stores of the main pass
+  // before these)
+  for (uint64_t e = stop + lane; e < ee; e += 64) {
+    uint32_t se;
+    uint64_t ve;
+    split(J, e, se, ve);
+    if (e < stored && first_fast<OP, KIND>(J, L.t, T, se, ve)) continue;
+    patch_store<OP>(J, e, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
+  }
+  // the elements before the first aligned one (block 0, wave 0)
+  if (blockIdx.x == 0 && wave == 0 && lane < head) {
+    uint32_t se;
+    uint64_t ve;
+    split(J, lane, se, ve);
+    patch_store<OP>(J, lane, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
+  }
+  if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane == 0) raise_flag(flags, ZG_FLAG_BUDGET);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -1034,33 +1476,47 @@ __global__ __launch_bounds__(512) void k_batch(DevRequest *R, const BatchHeader 
 
 template <int OP, int KIND>
 static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
-                                 uint32_t tile, uint32_t waves, uint32_t head,
+                                 uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
                                  hipStream_t stream) {
   uint64_t body = J.n_total > head ? J.n_total - head : 0;
-  uint64_t tiles = (body + tile - 1) / tile;
-  if (tiles == 0) tiles = 1;   // head-only jobs still need wave 0
-  uint64_t blocks = (tiles + waves - 1) / waves;
-  hipLaunchKernelGGL((k_fill<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * waves),
-                     (size_t)waves * (QCAP + TCAP) * sizeof(uint32_t), stream, J, T, dmax, flags,
-                     tile, head);
+  if constexpr (OP != OP_POLAR) {
+    // whole steps per wave
+    tile = (tile + BSTEP - 1) / BSTEP * BSTEP;
+    const uint64_t bt = (uint64_t)tile * waves;
+    uint64_t blocks = (body + bt - 1) / bt;
+    if (blocks == 0) blocks = 1;   // head-only jobs still need block 0
+    const uint32_t qc = qcap == 0 || qcap > BQ ? BQ : qcap;
+    hipLaunchKernelGGL((k_zig<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * waves), 0, stream, J,
+                       T, dmax, flags, tile, head, qc);
+  } else {
+    (void)qcap;
+    uint64_t tiles = (body + tile - 1) / tile;
+    if (tiles == 0) tiles = 1;   // head-only jobs still need wave 0
+    uint64_t blocks = (tiles + waves - 1) / waves;
+    hipLaunchKernelGGL((k_fill<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * waves),
+                       (size_t)waves * (QCAP + TCAP) * sizeof(uint32_t), stream, J, T, dmax, flags,
+                       tile, head);
+  }
   return hipGetLastError();
 }
 
 template <int OP>
 static hipError_t launch_kind(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
-                              uint32_t tile, uint32_t waves, uint32_t head, hipStream_t stream) {
+                              uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
+                              hipStream_t stream) {
   if (J.kind == ZG_JAVA_LCG48)
-    return launch_fill_op<OP, ZG_JAVA_LCG48>(J, T, dmax, flags, tile, waves, head, stream);
-  return launch_fill_op<OP, ZG_SPLITMIX64>(J, T, dmax, flags, tile, waves, head, stream);
+    return launch_fill_op<OP, ZG_JAVA_LCG48>(J, T, dmax, flags, tile, waves, head, qcap, stream);
+  return launch_fill_op<OP, ZG_SPLITMIX64>(J, T, dmax, flags, tile, waves, head, qcap, stream);
 }
 
 hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
-                       uint32_t tile, uint32_t waves, uint32_t head, hipStream_t stream) {
+                       uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
+                       hipStream_t stream) {
   switch (J.op) {
-    case OP_ZIG64: return launch_kind<OP_ZIG64>(J, T, dmax, flags, tile, waves, head, stream);
-    case OP_ZIG32: return launch_kind<OP_ZIG32>(J, T, dmax, flags, tile, waves, head, stream);
-    case OP_POLAR: return launch_kind<OP_POLAR>(J, T, dmax, flags, tile, waves, head, stream);
-    default: return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, stream);
+    case OP_ZIG64: return launch_kind<OP_ZIG64>(J, T, dmax, flags, tile, waves, head, qcap, stream);
+    case OP_ZIG32: return launch_kind<OP_ZIG32>(J, T, dmax, flags, tile, waves, head, qcap, stream);
+    case OP_POLAR: return launch_kind<OP_POLAR>(J, T, dmax, flags, tile, waves, head, qcap, stream);
+    default: return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, qcap, stream);
   }
 }
 

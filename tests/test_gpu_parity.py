@@ -200,3 +200,52 @@ def test_errors_are_reported(ctx, zg):
         ctx.zg_fill(out, kind=2, first_index=zg.ZG_LCG_WINDOW - 9)
     assert e.value.status == zg.ZG_ERANGE
     ctx.zg_fill(out[:0])   # n == 0 is a no-op
+
+
+@pytest.mark.parametrize("qcap", [1, 16, 200])
+def test_queue_overflow_path(ctx, zg, qcap):
+    """A workgroup queue too small for its slow elements: the overflowing
+    waves resolve the rest of their tiles themselves.  Output must not change
+    (checked against the default capacity bit for bit, and against the
+    oracle)."""
+    cases = [(zg.ZG_TUNE_FILL_F64, torch.float64, 100003, 1), (zg.ZG_TUNE_FILL_F32, torch.float32, 100003, 3),
+             (zg.ZG_TUNE_FILL_F64, torch.float64, 37 * 1000, 0)]
+    saved = {c: ctx.zg_get_tune(c) for c in (zg.ZG_TUNE_FILL_F64, zg.ZG_TUNE_FILL_F32, zg.ZG_TUNE_MUTATE)}
+    try:
+        for cls_t, tdt, n, offset in cases:
+            multi = n == 37 * 1000
+            outs = []
+            for cap in (0, qcap):
+                tile, waves, bpc, _ = saved[cls_t]
+                ctx.zg_set_tune(cls_t, tile, waves, bpc, cap)
+                out = dev_empty(n, tdt, offset)
+                out.fill_(float("nan"))
+                if multi:
+                    ctx.zg_fill_streams(out, 1000, 37, kind=1, seed=5, stream0=2, first_index=7)
+                else:
+                    ctx.zg_fill(out, kind=1, seed=5, stream=2, first_index=7)
+                outs.append(host(out).copy())
+            assert outs[0].tobytes() == outs[1].tobytes(), (cls_t, n, qcap)
+            if multi:
+                for k in range(37):
+                    want, cls, _ = orc.fill_f64(1, 5, 2 + k, 7, 1000)
+                    compare(outs[1][k * 1000:(k + 1) * 1000], want, cls, ("overflow streams", k))
+            elif tdt == torch.float64:
+                want, cls, _ = orc.fill_f64(1, 5, 2, 7, n)
+                compare(outs[1], want, cls, ("overflow f64", qcap))
+            else:
+                want, _, cls, _ = orc.fill_f32(1, 5, 2, 7, n)
+                compare(outs[1], want, cls, ("overflow f32", qcap))
+        # mutation
+        rng = np.random.Generator(np.random.PCG64(6))
+        x0 = rng.uniform(-3.0, 3.0, 50001)
+        tile, waves, bpc, _ = saved[zg.ZG_TUNE_MUTATE]
+        ctx.zg_set_tune(zg.ZG_TUNE_MUTATE, tile, waves, bpc, qcap)
+        x = dev_empty(x0.size, torch.float64, 1)
+        x.copy_(torch.from_numpy(x0))
+        ctx.zg_mutate(x, 0.25, kind=1, seed=3, stream=1, first_index=0)
+        want, cls, _ = orc.mutate(x0, 1, 3, 1, 0, 0.25)
+        compare(host(x), want, cls, ("overflow mutate", qcap))
+    finally:
+        for c, t in saved.items():
+            ctx.zg_set_tune(c, *t)
