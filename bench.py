@@ -35,8 +35,10 @@ def parse():
                    help="approximate CPU work of the oracle baseline sample")
     p.add_argument("--only", choices=["zig", "polar", "all"], default="all",
                    help="restrict the timed kernels (for profiling runs)")
-    p.add_argument("--serve-seconds", type=float, default=0.0,
-                   help="also run the serving loop for this long and report p50/p99")
+    p.add_argument("--serve-seconds", type=float, default=5.0,
+                   help="serving-loop run per mode (open-loop Poisson, 20k requests/s); 0 = skip")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the LCG, batch and mutation rows (profiling runs)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run three plain 1 GiB device copies (the known-size kernel "
                         "that scales the HBM byte counters) and exit")
@@ -100,6 +102,87 @@ def cpu_baseline(seconds):
     return {"value": done / dt, "unit": "variates/s", "cores": cores, "kind": "oracle",
             "sample": f"streams 0..{s - 1} of the 65536 x 4096 FP64 ziggurat variates "
                       f"(SplitMix64 seed 7): {done} variates in {dt:.1f} s"}
+
+
+def c3_lcg(ctx, Z, torch, steps, warmup):
+    """FP64 ziggurat over 2^28 variates of one LCG48 stream (seed 123456789)."""
+    n = 1 << 28
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def go():
+        ctx.zg_fill(out, kind=Z.ZG_JAVA_LCG48, seed=123456789, stream=0, first_index=0)
+
+    ms, _, _ = time_kernel(go, steps, warmup, torch)
+    del out
+    return {"workload": "ziggurat fill, 2^28 FP64, LCG48 seed 123456789, stream 0",
+            "value": n / (ms * 1e-3), "unit": "variates/s", "kernel_ms": ms,
+            "roofline": {"bound": "hbm", "achieved": 8.0 * n / (ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": 8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
+def c4_batch(ctx, Z, torch, reps):
+    """10^4 uneven requests (sizes clamp(2^(20u)), 70% FP64) plus one mutation
+    of 4096 x 1024 genes: one persistent batch launch against the same
+    requests issued one by one to the plain kernels."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(4))
+    m = 10000
+    u = rng.uniform(0.0, 1.0, m)
+    sizes = np.clip(np.floor(2.0 ** (20 * u)).astype(np.int64), 1, 1 << 20)
+    is64 = rng.uniform(0.0, 1.0, m) < 0.7
+    nbytes = [int(n) * (8 if f else 4) for n, f in zip(sizes, is64)]
+    offs = np.concatenate([[0], np.cumsum([(b + 255) // 256 * 256 for b in nbytes])])
+    genes = 4096 * 1024
+    pool = torch.empty(int(offs[-1]) + genes * 8 + 256, dtype=torch.uint8, device="cuda")
+    views = []
+    for k in range(m):
+        v = pool[int(offs[k]):int(offs[k]) + nbytes[k]]
+        views.append(v.view(torch.float64) if is64[k] else v.view(torch.float32))
+    g0 = int(offs[-1])
+    x = pool[g0:g0 + genes * 8].view(torch.float64)
+    # initial genes: -5 + 10 U from the uniform words of (seed 1, stream 65535)
+    w = torch.empty(genes, dtype=torch.int64, device="cuda")
+    ctx.zg_uniform_words(w, kind=Z.ZG_SPLITMIX64, seed=1, stream=65535)
+    x0 = -5.0 + 10.0 * ((w >> 11).to(torch.float64) * 2.0 ** -53)
+    del w
+    reqs = [{"out": views[k], "n": int(sizes[k]), "seed": 1000 + k, "stream": k,
+             "dtype": Z.ZG_F64 if is64[k] else Z.ZG_F32} for k in range(m)]
+    reqs.append({"out": x, "n": genes, "seed": 999, "stream": 0, "op": Z.ZG_OP_MUTATE,
+                 "sigma": 0.1, "dtype": Z.ZG_F64})
+
+    def batched():
+        x.copy_(x0)
+        ctx.zg_batch(reqs)
+
+    def plain():
+        x.copy_(x0)
+        for k in range(m):
+            ctx.zg_fill(views[k], seed=1000 + k, stream=k)
+        ctx.zg_mutate(x, 0.1, seed=999, stream=0)
+
+    variates = int(sizes.sum()) + genes
+    out = {"workload": "10^4 requests, sizes clamp(2^(20u),1,2^20), 70% FP64 / 30% FP32, "
+                       "plus a 4096x1024-gene mutation (sigma 0.1)", "variates": variates}
+    digests = {}
+    for name, fn in (("batched", batched), ("per_request", plain)):
+        ms, _, _ = time_kernel(fn, reps, 1, torch)
+        pool[:g0].zero_()
+        fn()
+        torch.cuda.synchronize()
+        digests[name] = int(pool[:g0 + genes * 8].view(torch.int64)[::997].sum().item())
+        out[name] = {"ms": ms, "variates_per_s": variates / (ms * 1e-3)}
+    out["same_bits"] = digests["batched"] == digests["per_request"]
+    out["speedup"] = out["per_request"]["ms"] / out["batched"]["ms"]
+    # the mutation row alone, against its own roofline (8 B read + 8 B written per gene)
+    ms, _, _ = time_kernel(lambda: ctx.zg_mutate(x, 0.1, seed=999, stream=0), 20, 3, torch)
+    out["mutation"] = {"genes": genes, "kernel_ms": ms, "genes_per_s": genes / (ms * 1e-3),
+                       "roofline": {"bound": "hbm", "achieved": 16.0 * genes / (ms * 1e-3) / 1e9,
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": 16.0 * genes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    del pool, views, x, x0
+    torch.cuda.empty_cache()
+    return out
 
 
 def read_traffic(kernel):
@@ -196,6 +279,11 @@ def main():
                          "kernel_ms": pms,
                          "roofline": {"bound": "hbm", "achieved": pach, "peak": HBM_PEAK_GBS,
                                       "unit": "GB/s", "frac": pach / HBM_PEAK_GBS}}
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        line["c3_lcg"] = c3_lcg(ctx, Z, torch, args.steps, args.warmup)
+        line["c4_batch"] = c4_batch(ctx, Z, torch, 3)
     if args.serve_seconds > 0:
         from paper_2405_19493_amd import serve_bench
         line["serving"] = serve_bench.run(ctx, duration_s=args.serve_seconds)

@@ -360,4 +360,81 @@ class Context:
         self._c(lib.zg_autotune(self.h, p, nbytes, 1 if use_cache else 0), "zg_autotune")
 
 
-__all__ = [n for n in dir() if n.startswith(("zg_", "ZG_"))] + ["Context", "ZgError", "lib"]
+def _completion(c):
+    return {"status": c.status, "done": bool(c.done), "d_out": c.d_out or 0,
+            "first_index": c.first_index, "arrival_s": c.arrival_s, "admit_s": c.admit_s,
+            "complete_s": c.complete_s}
+
+
+class Server:
+    """The serving loop of a context (zg_server_*): counter-keyed requests in,
+    outputs in a device arena, completions polled from the device."""
+
+    def __init__(self, ctx, mem_cap_bytes=1 << 30, max_inflight=4096, max_batch=1024,
+                 batch_window_us=200, n_streams=2, mode=ZG_SERVE_BATCHED):
+        self.ctx = ctx
+        cfg = ServerConfig(mem_cap_bytes, max_inflight, max_batch, batch_window_us, n_streams,
+                           mode, 0)
+        h = ctypes.c_void_p()
+        ctx._c(lib.zg_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)), "zg_server_create")
+        self.h = h
+
+    def submit(self, handle, n, dtype=ZG_F64, method=ZG_ZIGGURAT, arrival_s=0.0):
+        r = ServerRequest(n, handle, dtype, method, 0, float(arrival_s))
+        t = ctypes.c_uint64()
+        self.ctx._c(lib.zg_server_submit(self.h, ctypes.byref(r), ctypes.byref(t)),
+                    "zg_server_submit")
+        return t.value
+
+    def poll(self, ticket):
+        c = Completion()
+        self.ctx._c(lib.zg_server_poll(self.h, ticket, ctypes.byref(c)), "zg_server_poll")
+        return _completion(c)
+
+    def wait(self, ticket, timeout_s=30.0):
+        c = Completion()
+        self.ctx._c(lib.zg_server_wait(self.h, ticket, float(timeout_s), ctypes.byref(c)),
+                    "zg_server_wait")
+        return _completion(c)
+
+    def release(self, ticket):
+        self.ctx._c(lib.zg_server_release(self.h, ticket), "zg_server_release")
+
+    def drain(self):
+        self.ctx._c(lib.zg_server_drain(self.h), "zg_server_drain")
+
+    def now(self):
+        return lib.zg_server_now(self.h)
+
+    def stats(self):
+        st = ServerStats()
+        self.ctx._c(lib.zg_server_stats_get(self.h, ctypes.byref(st)), "zg_server_stats_get")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def output(self, completion, n, dtype=ZG_F64):
+        """A zero-copy torch view of a completed request's arena memory; it is
+        valid until the ticket is released."""
+
+        class _View:
+            pass
+
+        v = _View()
+        v.__cuda_array_interface__ = {
+            "shape": (n,), "typestr": "<f8" if dtype == ZG_F64 else "<f4",
+            "data": (completion["d_out"], False), "version": 2, "strides": None}
+        return torch.as_tensor(v, device="cuda")
+
+    def close(self):
+        if self.h:
+            lib.zg_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = [n for n in dir() if n.startswith(("zg_", "ZG_"))] + ["Context", "Server", "ZgError",
+                                                                 "lib"]

@@ -16,18 +16,6 @@ using namespace zg;
 
 namespace {
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
 const zg_tune DEFAULT_TUNE[ZG_TUNE_CLASSES] = {
     {1024, 16, 2, 0},   // FILL_F64
     {2048, 16, 2, 0},   // FILL_F32

@@ -23,7 +23,8 @@ void destroy_graph(hipGraph_t &g, hipGraphExec_t &x) {
 }  // namespace
 
 zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
-                     uint32_t *const *done_flags, uint32_t done_value, BatchPlan *plan) {
+                     uint32_t *const *done_flags, uint32_t done_value, BatchPlan *plan,
+                     uint64_t *const *first_host) {
   plan->reqs.clear();
   plan->index.clear();
   plan->total_tiles = 0;
@@ -88,6 +89,7 @@ zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
     d.remaining = (uint32_t)tiles;
     d.tile0 = plan->total_tiles;
     d.done_flag = done_flags ? done_flags[i] : nullptr;
+    d.first_host = first_host ? first_host[i] : nullptr;
     d.done_value = done_value;
     plan->total_tiles += tiles;
     plan->total_elems += r.n;

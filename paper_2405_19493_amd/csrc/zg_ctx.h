@@ -51,6 +51,19 @@ struct BatchSlot {
                    hipStream_t run_stream, hipEvent_t prep_done = nullptr);
 };
 
+// Makes `dev` current for the scope and restores the previous device.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
 zg_status hip_fail(const struct ::zg_ctx *ctx, hipError_t e, const char *what);
 uint64_t window_of(uint32_t kind);
 uint32_t max_streams_of(uint32_t kind);
@@ -62,8 +75,10 @@ zg_status launch_job(struct ::zg_ctx *ctx, const Job &J, hipStream_t stream);
 
 // done_flags (host-visible, optional): completion word of request i is
 // done_flags[i], written with done_value when its last tile finishes.
+// first_host (host-visible, optional): receives request i's first index.
 zg_status plan_batch(struct ::zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
-                     uint32_t *const *done_flags, uint32_t done_value, BatchPlan *plan);
+                     uint32_t *const *done_flags, uint32_t done_value, BatchPlan *plan,
+                     uint64_t *const *first_host = nullptr);
 zg_status acquire_slot(struct ::zg_ctx *ctx, BatchSlot **out);
 void release_slot(struct ::zg_ctx *ctx, BatchSlot *slot);
 

@@ -78,6 +78,7 @@ struct DevRequest {
   uint32_t last_of_handle;   // 1: advance the counter by off + n after the batch
   uint64_t limit;        // index window of the kind (first + n must stay <= limit)
   uint32_t *done_flag;   // host-visible completion word (may be null)
+  uint64_t *first_host;  // host-visible copy of the resolved first index (may be null)
   uint32_t done_value;
   uint32_t tiles;        // number of tiles of this request
   uint32_t status;       // 0 ok, ZG_FLAG_RANGE when skipped

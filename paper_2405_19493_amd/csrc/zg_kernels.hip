@@ -1399,6 +1399,8 @@ __global__ __launch_bounds__(1024) void k_reserve(DevRequest *R, const BatchHead
   for (uint32_t i = threadIdx.x; i < nreq; i += blockDim.x) {
     const DevRequest &r = R[i];
     if (r.handle >= 0 && r.last_of_handle) counters[r.handle] = r.job.first + r.job.n_total;
+    // ordered before the completion word by the batch kernel's system fence
+    if (r.first_host) *r.first_host = r.job.first;
   }
 }
 

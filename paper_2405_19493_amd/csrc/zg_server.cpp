@@ -1,0 +1,434 @@
+// Continuous-batching serving loop over the batch path.
+//
+// Callers submit counter-keyed requests ("n variates from this stream
+// handle").  A batcher thread admits them in arrival order while request
+// slots and output memory (one device arena) are free, gathers what arrived
+// within the batch window (or up to max_batch), and launches the batch as one
+// graph {descriptor upload, counter reservation, persistent batch kernel} on
+// one of n_streams HIP streams in turn, so several batches are in flight.
+// Every request has a host-mapped completion record that the device writes
+// (the resolved first index, then the completion word, with a system-scope
+// release); a completion thread polls the records of the requests in flight
+// and stamps their completion time.  In per-request mode every request is
+// launched alone through the same path (what a caller of zg_stream_fill per
+// request gets), which is the baseline the batched mode is measured against.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "zg_ctx.h"
+
+using namespace zg;
+
+namespace {
+
+constexpr uint64_t ARENA_ALIGN = 256;
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class Arena {
+ public:
+  void init(uint64_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(uint64_t bytes, uint64_t *off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const uint64_t rest = it->second - bytes, start = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[start] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<uint64_t, uint64_t> free_;
+};
+
+// Completion record in host memory, written by the device.
+struct HostRec {
+  uint32_t done;    // 0 until complete; bit 31: the request was skipped (index window)
+  uint32_t pad;
+  uint64_t first;   // first index the request received
+};
+
+struct Ticket {
+  zg_server_request req{};
+  uint64_t bytes = 0;
+  uint64_t off = 0;
+  int32_t rec = -1;      // completion record while in flight
+  bool has_mem = false;
+  zg_completion c{};
+};
+
+uint64_t elem_bytes(uint8_t dtype) { return dtype == ZG_F32 ? 4 : 8; }
+
+double percentile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double pos = q * (double)(v.size() - 1);
+  const size_t i = (size_t)pos;
+  const double f = pos - (double)i;
+  return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+struct zg_server {
+  zg_ctx *ctx = nullptr;
+  zg_server_config cfg{};
+  char *arena_base = nullptr;
+  Arena arena;
+  HostRec *recs = nullptr;      // host pointer
+  HostRec *d_recs = nullptr;    // the same records as the device sees them
+  std::vector<int32_t> free_recs;
+  std::vector<hipStream_t> streams;
+  uint32_t next_stream = 0;
+  std::chrono::steady_clock::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv_work;   // batcher: new requests or freed capacity
+  std::condition_variable cv_done;   // waiters: completions
+  std::condition_variable cv_poll;   // completion thread: new requests in flight
+  std::deque<uint64_t> pending;
+  std::unordered_map<uint64_t, Ticket> tickets;
+  std::vector<uint64_t> inflight;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+
+  uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, variates = 0;
+  uint64_t inflight_bytes = 0, peak_inflight_bytes = 0;
+  std::vector<double> latencies;
+  double first_arrival = -1.0, last_complete = 0.0;
+
+  std::thread batcher, completer;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void batch_loop();
+  void complete_loop();
+  // Marks a request complete (lock held).
+  void finish(uint64_t id, Ticket &t, int32_t status, uint64_t first);
+};
+
+void zg_server::finish(uint64_t id, Ticket &t, int32_t status, uint64_t first) {
+  t.c.status = status;
+  t.c.first_index = first;
+  t.c.complete_s = now();
+  t.c.done = 1;
+  if (t.rec >= 0) {
+    free_recs.push_back(t.rec);
+    t.rec = -1;
+  }
+  inflight.erase(std::remove(inflight.begin(), inflight.end(), id), inflight.end());
+  ++completed;
+  if (status == ZG_OK) variates += t.req.n;
+  latencies.push_back(t.c.complete_s - t.c.arrival_s);
+  last_complete = std::max(last_complete, t.c.complete_s);
+  cv_work.notify_one();
+  cv_done.notify_all();
+}
+
+void zg_server::batch_loop() {
+  DeviceGuard g(ctx->device);
+  const uint32_t limit = cfg.mode == ZG_SERVE_PER_REQUEST ? 1u : cfg.max_batch;
+  std::vector<uint64_t> batch;
+  std::vector<zg_request> reqs;
+  std::vector<uint32_t *> flags;
+  std::vector<uint64_t *> firsts;
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+    if (pending.empty()) break;   // stopping
+    if (cfg.mode == ZG_SERVE_BATCHED && cfg.batch_window_us && pending.size() < limit) {
+      // gather what arrives within the window after the oldest pending request
+      const double open = tickets[pending.front()].c.arrival_s;
+      const double close = std::max(open, now()) + 1e-6 * cfg.batch_window_us;
+      while (!stop && pending.size() < limit) {
+        const double left = close - now();
+        if (left <= 0) break;
+        cv_work.wait_for(lk, std::chrono::duration<double>(left));
+      }
+    }
+    // admit in arrival order while a record and arena space are free
+    batch.clear();
+    while (!pending.empty() && batch.size() < limit && !free_recs.empty()) {
+      const uint64_t id = pending.front();
+      Ticket &t = tickets[id];
+      uint64_t off = 0;
+      if (!arena.alloc(t.bytes, &off)) break;
+      t.off = off;
+      t.has_mem = true;
+      t.rec = free_recs.back();
+      free_recs.pop_back();
+      recs[t.rec].done = 0;
+      recs[t.rec].first = 0;
+      t.c.d_out = arena_base + off;
+      t.c.admit_s = now();
+      inflight_bytes += t.bytes;
+      peak_inflight_bytes = std::max(peak_inflight_bytes, inflight_bytes);
+      pending.pop_front();
+      batch.push_back(id);
+      inflight.push_back(id);
+    }
+    if (batch.empty()) {
+      // full: wait for a completion or a release
+      cv_work.wait(lk);
+      continue;
+    }
+    reqs.assign(batch.size(), zg_request{});
+    flags.assign(batch.size(), nullptr);
+    firsts.assign(batch.size(), nullptr);
+    for (size_t k = 0; k < batch.size(); ++k) {
+      const Ticket &t = tickets[batch[k]];
+      zg_request &r = reqs[k];
+      r.out = t.c.d_out;
+      r.n = t.req.n;
+      r.handle = (int32_t)t.req.handle;
+      r.dtype = t.req.dtype;
+      r.method = t.req.method;
+      r.op = ZG_OP_FILL;
+      flags[k] = &d_recs[t.rec].done;
+      firsts[k] = &d_recs[t.rec].first;
+    }
+    hipStream_t stream = streams[next_stream++ % streams.size()];
+    ++batches;
+    lk.unlock();
+    BatchPlan plan;
+    zg_status st = plan_batch(ctx, reqs.data(), (uint32_t)reqs.size(), flags.data(), 1u, &plan,
+                              firsts.data());
+    BatchSlot *slot = nullptr;
+    if (st == ZG_OK) st = acquire_slot(ctx, &slot);
+    if (st == ZG_OK) {
+      st = slot->launch(ctx, plan, stream, /*full=*/true, nullptr);
+      release_slot(ctx, slot);
+    }
+    lk.lock();
+    if (st != ZG_OK)
+      for (uint64_t id : batch) finish(id, tickets[id], st, 0);
+    else
+      cv_poll.notify_one();
+  }
+}
+
+void zg_server::complete_loop() {
+  std::vector<std::pair<uint64_t, int32_t>> watch;
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_poll.wait_for(lk, std::chrono::microseconds(200),
+                     [&] { return !inflight.empty() || (stop && pending.empty()); });
+    if (inflight.empty()) {
+      if (stop && pending.empty()) break;
+      continue;
+    }
+    watch.clear();
+    for (uint64_t id : inflight) watch.emplace_back(id, tickets[id].rec);
+    lk.unlock();
+    // poll the records without the lock; they are written by the device
+    std::vector<std::pair<size_t, uint32_t>> hits;
+    for (size_t k = 0; k < watch.size(); ++k) {
+      const uint32_t v = __atomic_load_n(&recs[watch[k].second].done, __ATOMIC_ACQUIRE);
+      if (v) hits.emplace_back(k, v);
+    }
+    if (hits.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    lk.lock();
+    for (auto &h : hits) {
+      const uint64_t id = watch[h.first].first;
+      auto it = tickets.find(id);
+      if (it == tickets.end() || it->second.c.done) continue;
+      const HostRec &rec = recs[watch[h.first].second];
+      const uint64_t first = __atomic_load_n(&rec.first, __ATOMIC_ACQUIRE);
+      finish(id, it->second, (h.second & 0x80000000u) ? ZG_ERANGE : ZG_OK, first);
+    }
+  }
+}
+
+extern "C" {
+
+zg_status zg_server_create(zg_ctx *ctx, const zg_server_config *cfg, zg_server **out) {
+  if (!ctx || !cfg || !out) return ZG_EINVAL;
+  if (cfg->mem_cap_bytes < ARENA_ALIGN || cfg->max_inflight == 0 || cfg->max_inflight > 1u << 20 ||
+      cfg->max_batch == 0 || cfg->max_batch > ZG_MAX_BATCH || cfg->n_streams < 1 ||
+      cfg->n_streams > 16 || cfg->mode > ZG_SERVE_PER_REQUEST)
+    return ZG_EINVAL;
+  DeviceGuard g(ctx->device);
+  zg_server *s = new zg_server();
+  s->ctx = ctx;
+  s->cfg = *cfg;
+  s->cfg.mem_cap_bytes &= ~(ARENA_ALIGN - 1);
+  s->t0 = std::chrono::steady_clock::now();
+  hipError_t e = hipMalloc((void **)&s->arena_base, s->cfg.mem_cap_bytes);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&s->recs, sizeof(HostRec) * cfg->max_inflight,
+                      hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->d_recs, s->recs, 0);
+  for (uint32_t k = 0; k < cfg->n_streams && e == hipSuccess; ++k) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) s->streams.push_back(st);
+  }
+  if (e != hipSuccess) {
+    zg_status st = hip_fail(ctx, e, "server create");
+    for (hipStream_t st2 : s->streams) (void)hipStreamDestroy(st2);
+    if (s->recs) (void)hipHostFree(s->recs);
+    if (s->arena_base) (void)hipFree(s->arena_base);
+    delete s;
+    return st == ZG_OK ? ZG_EHIP : st;
+  }
+  std::memset(s->recs, 0, sizeof(HostRec) * cfg->max_inflight);
+  s->arena.init(s->cfg.mem_cap_bytes);
+  for (int32_t k = (int32_t)cfg->max_inflight - 1; k >= 0; --k) s->free_recs.push_back(k);
+  s->batcher = std::thread([s] { s->batch_loop(); });
+  s->completer = std::thread([s] { s->complete_loop(); });
+  *out = s;
+  return ZG_OK;
+}
+
+zg_status zg_server_submit(zg_server *s, const zg_server_request *req, uint64_t *ticket) {
+  if (!s || !req || !ticket) return ZG_EINVAL;
+  if (req->dtype > ZG_F32 || req->method > ZG_POLAR) return ZG_EINVAL;
+  if (req->method == ZG_POLAR && req->dtype == ZG_F32) return ZG_EINVAL;
+  const uint64_t bytes =
+      (req->n * elem_bytes(req->dtype) + ARENA_ALIGN - 1) & ~(ARENA_ALIGN - 1);
+  if (req->n > (1ull << 40) || bytes > s->cfg.mem_cap_bytes) return ZG_EINVAL;
+  {
+    std::lock_guard<std::mutex> hl(s->ctx->mu);
+    if (req->handle >= ZG_MAX_HANDLES || !s->ctx->handles[req->handle].open) return ZG_ENOENT;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return ZG_ESTATE;
+  const uint64_t id = s->next_ticket++;
+  Ticket &t = s->tickets[id];
+  t.req = *req;
+  t.bytes = bytes;
+  t.c.arrival_s = req->arrival_s > 0.0 ? req->arrival_s : s->now();
+  if (s->first_arrival < 0.0 || t.c.arrival_s < s->first_arrival) s->first_arrival = t.c.arrival_s;
+  ++s->submitted;
+  *ticket = id;
+  if (req->n == 0) {
+    t.c.admit_s = s->now();
+    s->finish(id, t, ZG_OK, 0);
+    return ZG_OK;
+  }
+  s->pending.push_back(id);
+  s->cv_work.notify_one();
+  return ZG_OK;
+}
+
+zg_status zg_server_poll(zg_server *s, uint64_t ticket, zg_completion *out) {
+  if (!s || !out) return ZG_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return ZG_ENOENT;
+  *out = it->second.c;
+  return ZG_OK;
+}
+
+zg_status zg_server_wait(zg_server *s, uint64_t ticket, double timeout_s, zg_completion *out) {
+  if (!s) return ZG_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto done = [&] {
+    auto it = s->tickets.find(ticket);
+    return it == s->tickets.end() || it->second.c.done;
+  };
+  if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) return ZG_EBUSY;
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return ZG_ENOENT;
+  if (out) *out = it->second.c;
+  return ZG_OK;
+}
+
+zg_status zg_server_release(zg_server *s, uint64_t ticket) {
+  if (!s) return ZG_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return ZG_ENOENT;
+  if (!it->second.c.done) return ZG_EBUSY;
+  if (it->second.has_mem) {
+    s->arena.release(it->second.off, it->second.bytes);
+    s->inflight_bytes -= it->second.bytes;
+  }
+  s->tickets.erase(it);
+  s->cv_work.notify_one();
+  return ZG_OK;
+}
+
+zg_status zg_server_drain(zg_server *s) {
+  if (!s) return ZG_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->pending.empty() && s->inflight.empty(); });
+  return ZG_OK;
+}
+
+zg_status zg_server_stats_get(zg_server *s, zg_server_stats *out) {
+  if (!s || !out) return ZG_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->rejected = s->rejected;
+  out->batches = s->batches;
+  out->variates = s->variates;
+  out->inflight_bytes = s->inflight_bytes;
+  out->peak_inflight_bytes = s->peak_inflight_bytes;
+  out->p50_latency_s = percentile(s->latencies, 0.50);
+  out->p99_latency_s = percentile(s->latencies, 0.99);
+  out->max_latency_s =
+      s->latencies.empty() ? 0.0 : *std::max_element(s->latencies.begin(), s->latencies.end());
+  out->first_arrival_s = s->first_arrival < 0.0 ? 0.0 : s->first_arrival;
+  out->last_complete_s = s->last_complete;
+  return ZG_OK;
+}
+
+double zg_server_now(const zg_server *s) { return s ? s->now() : 0.0; }
+
+zg_status zg_server_destroy(zg_server *s) {
+  if (!s) return ZG_OK;
+  zg_server_drain(s);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  s->cv_poll.notify_all();
+  if (s->batcher.joinable()) s->batcher.join();
+  if (s->completer.joinable()) s->completer.join();
+  DeviceGuard g(s->ctx->device);
+  for (hipStream_t st : s->streams) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  if (s->recs) (void)hipHostFree(s->recs);
+  if (s->arena_base) (void)hipFree(s->arena_base);
+  delete s;
+  return ZG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+"""The serving loop (zg_server_*) through the C ABI: counter continuation per
+stream handle, bits equal to the request run alone, both modes, admission."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import coracle as orc
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(rng, count, n_handles, max_log2=16):
+    sizes = np.exp(rng.uniform(np.log(16), np.log(2 ** max_log2), count)).astype(np.int64)
+    dtypes = (rng.uniform(0, 1, count) >= 0.7).astype(np.int64)   # 1 = FP32
+    hidx = rng.integers(0, n_handles, count)
+    return sizes, dtypes, hidx
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_server_bits_and_counters(ctx, zg, mode):
+    rng = np.random.Generator(np.random.PCG64(21 + mode))
+    n_handles = 7
+    seeds = [100 + h for h in range(n_handles)]
+    handles = [ctx.zg_stream_open(seeds[h], 10 + h, zg.ZG_SPLITMIX64) for h in range(n_handles)]
+    sizes, dtypes, hidx = _requests(rng, 150, n_handles)
+    srv = zg.Server(ctx, mem_cap_bytes=64 << 20, max_inflight=64, max_batch=32,
+                    batch_window_us=300, n_streams=2, mode=mode)
+    try:
+        tickets = [srv.submit(handles[int(h)], int(n), int(d)) for n, d, h in zip(sizes, dtypes, hidx)]
+        expect_first = {}
+        running = [0] * n_handles
+        for k, (n, h) in enumerate(zip(sizes, hidx)):
+            expect_first[k] = running[int(h)]
+            running[int(h)] += int(n)
+        for k, t in enumerate(tickets):
+            c = srv.wait(t, 60.0)
+            assert c["done"] and c["status"] == zg.ZG_OK, (k, c)
+            assert c["first_index"] == expect_first[k], (k, c["first_index"], expect_first[k])
+            assert c["admit_s"] >= c["arrival_s"] and c["complete_s"] >= c["admit_s"]
+            got = srv.output(c, int(sizes[k]), int(dtypes[k])).clone()
+            h = int(hidx[k])
+            alone = torch.empty_like(got)
+            ctx.zg_fill(alone, kind=zg.ZG_SPLITMIX64, seed=seeds[h], stream=10 + h,
+                        first_index=c["first_index"])
+            torch.cuda.synchronize()
+            assert torch.equal(alone.view(torch.uint8), got.view(torch.uint8)), k
+            if k % 25 == 0:
+                n = int(sizes[k])
+                if dtypes[k] == 0:
+                    want, cls, _ = orc.fill_f64(orc.SM64, seeds[h], 10 + h, c["first_index"], n)
+                else:
+                    want, _, cls, _ = orc.fill_f32(orc.SM64, seeds[h], 10 + h, c["first_index"], n)
+                compare(got.cpu().numpy(), want, cls, ("server", mode, k))
+            srv.release(t)
+        srv.drain()
+        st = srv.stats()
+        assert st["completed"] == len(tickets) and st["submitted"] == len(tickets)
+        assert st["variates"] == int(sizes.sum())
+        assert st["inflight_bytes"] == 0
+        assert 0 < st["p50_latency_s"] <= st["p99_latency_s"] <= st["max_latency_s"]
+        if mode == 1:
+            assert st["batches"] == len(tickets)
+        for h in range(n_handles):
+            assert ctx.zg_stream_get_counter(handles[h]) == running[h]
+    finally:
+        srv.close()
+        for h in handles:
+            ctx.zg_stream_close(h)
+
+
+def test_server_admission_and_errors(ctx, zg):
+    h = ctx.zg_stream_open(9, 3, zg.ZG_SPLITMIX64)
+    # the arena holds two 512 KiB requests at a time: the rest wait for releases
+    srv = zg.Server(ctx, mem_cap_bytes=1 << 20, max_inflight=16, max_batch=8,
+                    batch_window_us=0, n_streams=2, mode=0)
+    try:
+        with pytest.raises(zg.ZgError) as e:
+            srv.submit(h, (1 << 20) // 8 + 1)          # larger than the arena
+        assert e.value.status == zg.ZG_EINVAL
+        with pytest.raises(zg.ZgError) as e:
+            srv.submit(h, 100, dtype=zg.ZG_F32, method=zg.ZG_POLAR)
+        assert e.value.status == zg.ZG_EINVAL
+        with pytest.raises(zg.ZgError) as e:
+            srv.submit(60000, 100)                      # not an open handle
+        assert e.value.status == zg.ZG_ENOENT
+        n = (512 << 10) // 8
+        tickets = [srv.submit(h, n) for _ in range(6)]
+        firsts = []
+        for t in tickets:
+            c = srv.wait(t, 60.0)
+            assert c["status"] == zg.ZG_OK
+            firsts.append(c["first_index"])
+            srv.release(t)
+        assert firsts == [k * n for k in range(6)]
+        st = srv.stats()
+        assert st["peak_inflight_bytes"] <= 1 << 20
+        z = srv.submit(h, 0)                            # empty request: completes at once
+        assert srv.poll(z)["done"]
+        srv.release(z)
+        with pytest.raises(zg.ZgError) as e:
+            srv.release(z)
+        assert e.value.status == zg.ZG_ENOENT
+    finally:
+        srv.close()
+        ctx.zg_stream_close(h)
+
+
+def test_server_range_error_is_reported(ctx, zg):
+    """A request that would run past its stream's index window completes with
+    ZG_ERANGE (sets the sticky range flag, writes nothing); its index range is
+    still reserved, as the batch path does for every counter-keyed request."""
+    h = ctx.zg_stream_open(4, 4, zg.ZG_JAVA_LCG48)
+    ctx.zg_stream_set_counter(h, zg.ZG_LCG_WINDOW - 100)
+    srv = zg.Server(ctx, mem_cap_bytes=1 << 20, max_inflight=4, max_batch=4, batch_window_us=0,
+                    n_streams=2, mode=0)
+    try:
+        ctx.zg_error_flags(clear=True)
+        t = srv.submit(h, 60)
+        c = srv.wait(t, 60.0)
+        assert c["status"] == zg.ZG_OK and c["first_index"] == zg.ZG_LCG_WINDOW - 100
+        srv.release(t)
+        t = srv.submit(h, 1000)
+        c = srv.wait(t, 60.0)
+        assert c["status"] == zg.ZG_ERANGE and c["first_index"] == zg.ZG_LCG_WINDOW - 40
+        srv.release(t)
+        assert ctx.zg_error_flags(clear=True) & zg.ZG_FLAG_RANGE
+        assert ctx.zg_stream_get_counter(h) == zg.ZG_LCG_WINDOW - 40 + 1000
+    finally:
+        srv.close()
+        ctx.zg_stream_close(h)
