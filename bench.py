@@ -151,9 +151,11 @@ def c4_batch(ctx, Z, torch, reps):
     reqs.append({"out": x, "n": genes, "seed": 999, "stream": 0, "op": Z.ZG_OP_MUTATE,
                  "sigma": 0.1, "dtype": Z.ZG_F64})
 
+    creqs = ctx.zg_batch_prepare(reqs)
+
     def batched():
         x.copy_(x0)
-        ctx.zg_batch(reqs)
+        ctx.zg_batch(creqs)
 
     def plain():
         x.copy_(x0)

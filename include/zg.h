@@ -318,6 +318,16 @@ zg_status zg_server_drain(zg_server *srv);
 zg_status zg_server_stats_get(zg_server *srv, zg_server_stats *out);
 /* Seconds on the server's monotonic clock. */
 double zg_server_now(const zg_server *srv);
+/* Open-loop replay of a request trace (load generation for the serving
+ * benchmark): submits reqs[k] when reqs[k].arrival_s seconds have passed
+ * since the call, from the calling thread, so submission itself adds no
+ * queueing; releases each output as soon as it completes (the arena then
+ * bounds only the bytes in flight); returns once all have completed, or
+ * ZG_EBUSY when timeout_s passes first.  first_out (host, optional, n
+ * entries) receives each request's first index.  Returns the first request
+ * error seen, if any (the other requests still run). */
+zg_status zg_server_replay(zg_server *srv, const zg_server_request *reqs, uint32_t n,
+                           uint64_t *first_out, double timeout_s);
 /* Stops the threads (after draining), frees the arena and the streams. */
 zg_status zg_server_destroy(zg_server *srv);
 

@@ -155,6 +155,7 @@ def _load():
         "zg_server_drain": [P],
         "zg_server_stats_get": [P, P],
         "zg_server_destroy": [P],
+        "zg_server_replay": [P, P, U32, P, D],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name, None)
@@ -324,9 +325,10 @@ class Context:
         self._c(lib.zg_stream_set_counter(self.h, handle, counter), "zg_stream_set_counter")
 
     # -------------------------------------------------------------- batch
-    def zg_batch(self, requests, want_first=False, hip_stream=None):
-        """requests: list of dicts with keys out (tensor), n, seed, stream,
-        first_index, sigma, handle, dtype, method, kind, op."""
+    @staticmethod
+    def zg_batch_prepare(requests):
+        """The C request array of a list of request dicts (reusable across
+        zg_batch calls)."""
         arr = (Request * len(requests))()
         for i, r in enumerate(requests):
             out = r["out"]
@@ -341,6 +343,13 @@ class Context:
             arr[i].method = r.get("method", ZG_ZIGGURAT)
             arr[i].kind = r.get("kind", ZG_SPLITMIX64)
             arr[i].op = r.get("op", ZG_OP_FILL)
+        return arr
+
+    def zg_batch(self, requests, want_first=False, hip_stream=None):
+        """requests: list of dicts with keys out (tensor), n, seed, stream,
+        first_index, sigma, handle, dtype, method, kind, op; or an array from
+        zg_batch_prepare."""
+        arr = requests if isinstance(requests, ctypes.Array) else self.zg_batch_prepare(requests)
         first = (ctypes.c_uint64 * len(requests))() if want_first else None
         self._c(lib.zg_batch(self.h, arr, len(requests), first, _stream(hip_stream)), "zg_batch")
         return list(first) if want_first else None
@@ -405,6 +414,22 @@ class Server:
 
     def now(self):
         return lib.zg_server_now(self.h)
+
+    def replay(self, handles, sizes, dtypes, arrivals, timeout_s=600.0, want_first=False):
+        """Open-loop replay of a trace (numpy arrays of equal length; arrival
+        times in seconds from the call)."""
+        n = len(sizes)
+        arr = (ServerRequest * n)()
+        for k in range(n):
+            arr[k].n = int(sizes[k])
+            arr[k].handle = int(handles[k])
+            arr[k].dtype = int(dtypes[k])
+            arr[k].method = ZG_ZIGGURAT
+            arr[k].arrival_s = float(arrivals[k])
+        first = (ctypes.c_uint64 * n)() if want_first else None
+        self.ctx._c(lib.zg_server_replay(self.h, arr, n, first, float(timeout_s)),
+                    "zg_server_replay")
+        return list(first) if want_first else None
 
     def stats(self):
         st = ServerStats()

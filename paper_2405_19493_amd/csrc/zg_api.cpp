@@ -420,7 +420,7 @@ zg_status zg_set_tune(zg_ctx *ctx, int cls, const zg_tune *in) {
   if (in->tile == 0 || in->tile % ch || in->tile > (1u << 19)) return ZG_EINVAL;
   if (in->waves_per_block < 1 || in->waves_per_block > 16) return ZG_EINVAL;
   if (in->batch_blocks_per_cu < 1 || in->batch_blocks_per_cu > 8) return ZG_EINVAL;
-  if (cls == ZG_TUNE_BATCH && (in->tile % 256 || in->waves_per_block > 8)) return ZG_EINVAL;
+  if (cls == ZG_TUNE_BATCH && in->tile % 256) return ZG_EINVAL;
   if (in->queue_cap > 2048) return ZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->tune[cls] = *in;

@@ -13,6 +13,8 @@ namespace zg {
 
 namespace {
 constexpr uint32_t SLOT_COUNT = 8;
+// batches of at most this many requests are launched directly, not as a graph
+constexpr size_t DIRECT_MAX = 8;
 
 void destroy_graph(hipGraph_t &g, hipGraphExec_t &x) {
   if (x) (void)hipGraphExecDestroy(x);
@@ -27,7 +29,7 @@ zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
                      uint64_t *const *first_host) {
   plan->reqs.clear();
   plan->index.clear();
-  plan->total_tiles = 0;
+  plan->items.clear();
   plan->total_elems = 0;
   const zg_tune bt = ctx->tune[ZG_TUNE_BATCH];
   std::unordered_map<int32_t, size_t> last_of;   // handle -> planned index of its last request
@@ -79,24 +81,45 @@ zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
       off += r.n;
       last_of[r.handle] = plan->reqs.size();
     }
-    d.tile = op == OP_ZIG32 ? 2 * bt.tile : bt.tile;
+    // whole 256-element steps per wave; FP32 tiles hold twice the elements
+    const uint32_t wave_tile = op == OP_ZIG32 ? 2 * bt.tile : bt.tile;
+    d.tile = (wave_tile + 255) / 256 * 256;
     d.head = head_of(r.out, op, r.n);
-    uint64_t body = r.n - d.head;
-    uint64_t tiles = (body + d.tile - 1) / d.tile;
+    const uint64_t body = r.n - d.head;
+    const uint64_t per = (uint64_t)d.tile * bt.waves_per_block;
+    uint64_t tiles = (body + per - 1) / per;
     if (tiles == 0) tiles = 1;
     if (tiles > 0xFFFFFFFFull) return ZG_EINVAL;
     d.tiles = (uint32_t)tiles;
-    d.remaining = (uint32_t)tiles;
-    d.tile0 = plan->total_tiles;
     d.done_flag = done_flags ? done_flags[i] : nullptr;
     d.first_host = first_host ? first_host[i] : nullptr;
     d.done_value = done_value;
-    plan->total_tiles += tiles;
     plan->total_elems += r.n;
     plan->reqs.push_back(d);
     plan->index.push_back(i);
   }
   for (auto &kv : last_of) plan->reqs[kv.second].last_of_handle = 1;
+  // work items, grouped by class
+  uint64_t total = 0;
+  for (int c = 0; c < BATCH_CLASSES; ++c) plan->cls_cnt[c] = 0;
+  for (const DevRequest &d : plan->reqs) {
+    plan->cls_cnt[batch_class(d.job.op, d.job.kind)] += d.tiles;
+    total += d.tiles;
+  }
+  if (total > 0xFFFFFFFFull) return ZG_EINVAL;
+  uint32_t acc = 0;
+  for (int c = 0; c < BATCH_CLASSES; ++c) {
+    plan->cls_off[c] = acc;
+    acc += plan->cls_cnt[c];
+  }
+  plan->items.resize(total);
+  uint32_t fill[BATCH_CLASSES];
+  for (int c = 0; c < BATCH_CLASSES; ++c) fill[c] = plan->cls_off[c];
+  for (size_t k = 0; k < plan->reqs.size(); ++k) {
+    const DevRequest &d = plan->reqs[k];
+    uint32_t &f = fill[batch_class(d.job.op, d.job.kind)];
+    for (uint32_t j = 0; j < d.tiles; ++j) plan->items[f++] = ((uint64_t)k << 32) | j;
+  }
   return ZG_OK;
 }
 
@@ -145,6 +168,8 @@ void BatchSlot::invalidate_graphs() {
   destroy_graph(g_prep, x_prep);
   destroy_graph(g_run, x_run);
   cpy_full = cpy_prep = nullptr;
+  for (int c = 0; c < BATCH_CLASSES; ++c) cls_full[c] = cls_run[c] = nullptr;
+  mask_full = mask_run = 0xFFu;
 }
 
 void BatchSlot::release() {
@@ -158,26 +183,30 @@ void BatchSlot::release() {
   recorded = false;
 }
 
-zg_status BatchSlot::ensure(zg_ctx *ctx, size_t nreq) {
+zg_status BatchSlot::ensure(zg_ctx *ctx, size_t nreq, size_t nitems) {
   if (!done) {
     hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(ctx, e, "slot event");
   }
-  if (nreq <= cap) return ZG_OK;
+  if (nreq <= cap && nitems <= item_cap) return ZG_OK;
   size_t want = std::max<size_t>(nreq, 256);
-  want = std::min<size_t>(std::max(want, cap * 2), ZG_MAX_BATCH);
+  want = std::min<size_t>(std::max(want, nreq <= cap ? cap : cap * 2), ZG_MAX_BATCH);
   if (want < nreq) return ZG_EINVAL;
+  size_t want_items = std::max<size_t>(std::max<size_t>(nitems, 4096),
+                                       nitems <= item_cap ? item_cap : item_cap * 2);
   invalidate_graphs();
   if (h_buf) (void)hipHostFree(h_buf);
   if (d_buf) (void)hipFree(d_buf);
   h_buf = d_buf = nullptr;
-  cap = 0;
-  size_t bytes = sizeof(BatchHeader) + want * sizeof(DevRequest);
+  cap = item_cap = 0;
+  size_t bytes = sizeof(BatchHeader) + want * sizeof(DevRequest) + want_items * sizeof(uint64_t);
+  if (bytes > 0xFFFFFFFFull) return ZG_EINVAL;
   hipError_t e = hipHostMalloc(&h_buf, bytes, hipHostMallocDefault);
   if (e != hipSuccess) return hip_fail(ctx, e, "slot staging");
   e = hipMalloc(&d_buf, bytes);
   if (e != hipSuccess) return hip_fail(ctx, e, "slot device buffer");
   cap = want;
+  item_cap = want_items;
   return ZG_OK;
 }
 
@@ -200,26 +229,40 @@ zg_status BatchSlot::build_graphs(zg_ctx *ctx) {
   kr.kernelParams = reserve_args;
   kr.extra = nullptr;
 
-  void *batch_args[] = {&dR, &dH, &T, &flags};
-  hipKernelNodeParams kb{};
-  kb.func = (void *)kernel_batch();
-  kb.gridDim = dim3((uint32_t)(ctx->num_cus * bt.batch_blocks_per_cu));
-  kb.blockDim = dim3(64 * bt.waves_per_block);
-  kb.sharedMemBytes = (unsigned)batch_lds_bytes(bt.waves_per_block);
-  kb.kernelParams = batch_args;
-  kb.extra = nullptr;
+  void *class_args[] = {&dR, &dH, &T, &flags};
+  hipKernelNodeParams kc[BATCH_CLASSES];
+  for (int c = 0; c < BATCH_CLASSES; ++c) {
+    kc[c] = hipKernelNodeParams{};
+    kc[c].func = (void *)kernel_batch_class(c);
+    kc[c].gridDim = dim3((uint32_t)(ctx->num_cus * bt.batch_blocks_per_cu));
+    kc[c].blockDim = dim3(64 * bt.waves_per_block);
+    kc[c].sharedMemBytes = (unsigned)batch_class_lds_bytes(c, bt.waves_per_block);
+    kc[c].kernelParams = class_args;
+    kc[c].extra = nullptr;
+  }
 
+  void *complete_args[] = {&dR, &dH};
+  hipKernelNodeParams kd{};
+  kd.func = (void *)kernel_complete();
+  kd.gridDim = dim3(ZG_MAX_BATCH / 256);
+  kd.blockDim = dim3(256);
+  kd.sharedMemBytes = 0;
+  kd.kernelParams = complete_args;
+  kd.extra = nullptr;
+
+  // full = {copy -> reserve -> class kernels -> completion words};
+  // prep = {copy -> reserve}; run = {class kernels -> completion words}
   hipError_t e;
-  hipGraphNode_t nr, nb;
-  // full graph: copy -> reserve -> batch
+  hipGraphNode_t nr, nd;
   e = hipGraphCreate(&g_full, 0);
   if (e == hipSuccess)
     e = hipGraphAddMemcpyNode1D(&cpy_full, g_full, nullptr, 0, d_buf, h_buf, bytes,
                                 hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipGraphAddKernelNode(&nr, g_full, &cpy_full, 1, &kr);
-  if (e == hipSuccess) e = hipGraphAddKernelNode(&nb, g_full, &nr, 1, &kb);
+  for (int c = 0; c < BATCH_CLASSES && e == hipSuccess; ++c)
+    e = hipGraphAddKernelNode(&cls_full[c], g_full, &nr, 1, &kc[c]);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&nd, g_full, cls_full, BATCH_CLASSES, &kd);
   if (e == hipSuccess) e = hipGraphInstantiate(&x_full, g_full, nullptr, nullptr, 0);
-  // split graphs for the serving loop: copy -> reserve, then batch
   if (e == hipSuccess) e = hipGraphCreate(&g_prep, 0);
   if (e == hipSuccess)
     e = hipGraphAddMemcpyNode1D(&cpy_prep, g_prep, nullptr, 0, d_buf, h_buf, bytes,
@@ -227,8 +270,11 @@ zg_status BatchSlot::build_graphs(zg_ctx *ctx) {
   if (e == hipSuccess) e = hipGraphAddKernelNode(&nr, g_prep, &cpy_prep, 1, &kr);
   if (e == hipSuccess) e = hipGraphInstantiate(&x_prep, g_prep, nullptr, nullptr, 0);
   if (e == hipSuccess) e = hipGraphCreate(&g_run, 0);
-  if (e == hipSuccess) e = hipGraphAddKernelNode(&nb, g_run, nullptr, 0, &kb);
+  for (int c = 0; c < BATCH_CLASSES && e == hipSuccess; ++c)
+    e = hipGraphAddKernelNode(&cls_run[c], g_run, nullptr, 0, &kc[c]);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&nd, g_run, cls_run, BATCH_CLASSES, &kd);
   if (e == hipSuccess) e = hipGraphInstantiate(&x_run, g_run, nullptr, nullptr, 0);
+  mask_full = mask_run = 0xFFu;
   if (e != hipSuccess) {
     invalidate_graphs();
     return hip_fail(ctx, e, "batch graph build");
@@ -238,7 +284,7 @@ zg_status BatchSlot::build_graphs(zg_ctx *ctx) {
 
 zg_status BatchSlot::launch(zg_ctx *ctx, const BatchPlan &plan, hipStream_t stream, bool full,
                             hipStream_t run_stream, hipEvent_t prep_done) {
-  zg_status st = ensure(ctx, plan.reqs.size());
+  zg_status st = ensure(ctx, plan.reqs.size(), plan.items.size());
   if (st != ZG_OK) return st;
   st = build_graphs(ctx);
   if (st != ZG_OK) return st;
@@ -246,11 +292,60 @@ zg_status BatchSlot::launch(zg_ctx *ctx, const BatchPlan &plan, hipStream_t stre
   std::memset(H, 0, sizeof(*H));
   H->nreq = (uint32_t)plan.reqs.size();
   H->dmax = ctx->dmax;
-  H->total_tiles = plan.total_tiles;
+  H->n_items = (uint32_t)plan.items.size();
+  H->items_off = (uint32_t)(sizeof(BatchHeader) + plan.reqs.size() * sizeof(DevRequest));
+  for (int c = 0; c < BATCH_CLASSES; ++c) {
+    H->cls_off[c] = plan.cls_off[c];
+    H->cls_cnt[c] = plan.cls_cnt[c];
+  }
   std::memcpy((char *)h_buf + sizeof(BatchHeader), plan.reqs.data(),
               plan.reqs.size() * sizeof(DevRequest));
-  size_t bytes = sizeof(BatchHeader) + plan.reqs.size() * sizeof(DevRequest);
+  // the items follow the descriptors
+  std::memcpy((char *)h_buf + H->items_off, plan.items.data(),
+              plan.items.size() * sizeof(uint64_t));
+  size_t bytes = H->items_off + plan.items.size() * sizeof(uint64_t);
   hipError_t e;
+  if (full && plan.reqs.size() <= DIRECT_MAX) {
+    // a few requests: plain launches of the classes with work, each grid
+    // sized to its tiles (cheaper than updating and launching the graph)
+    const zg_tune bt = ctx->tune[ZG_TUNE_BATCH];
+    const uint32_t cap_blocks = (uint32_t)(ctx->num_cus * bt.batch_blocks_per_cu);
+    BatchHeader *dH = (BatchHeader *)d_buf;
+    DevRequest *dR = d_reqs();
+    DevTables *T = ctx->d_tables;
+    uint32_t *flags = ctx->d_flags;
+    uint64_t *counters = ctx->d_counters;
+    void *reserve_args[] = {&dR, &dH, &counters, &flags};
+    void *class_args[] = {&dR, &dH, &T, &flags};
+    void *complete_args[] = {&dR, &dH};
+    e = hipMemcpyAsync(d_buf, h_buf, bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipLaunchKernel(kernel_reserve(), dim3(1), dim3(1024), reserve_args, 0, stream);
+    for (int c = 0; c < BATCH_CLASSES && e == hipSuccess; ++c) {
+      if (!plan.cls_cnt[c]) continue;
+      const uint32_t grid = plan.cls_cnt[c] < cap_blocks ? plan.cls_cnt[c] : cap_blocks;
+      e = hipLaunchKernel(kernel_batch_class(c), dim3(grid), dim3(64 * bt.waves_per_block),
+                          class_args, batch_class_lds_bytes(c, bt.waves_per_block), stream);
+    }
+    if (e == hipSuccess)
+      e = hipLaunchKernel(kernel_complete(), dim3(1), dim3(256), complete_args, 0, stream);
+    if (e == hipSuccess) e = hipEventRecord(done, stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch launch");
+    recorded = true;
+    return ZG_OK;
+  }
+  // only the classes with work run
+  uint32_t mask = 0;
+  for (int c = 0; c < BATCH_CLASSES; ++c)
+    if (plan.cls_cnt[c]) mask |= 1u << c;
+  hipGraphExec_t xg = full ? x_full : x_run;
+  hipGraphNode_t *nodes = full ? cls_full : cls_run;
+  uint32_t &cur = full ? mask_full : mask_run;
+  e = hipSuccess;
+  for (int c = 0; c < BATCH_CLASSES && e == hipSuccess; ++c)
+    if (((cur ^ mask) >> c) & 1u) e = hipGraphNodeSetEnabled(xg, nodes[c], (mask >> c) & 1u);
+  if (e != hipSuccess) return hip_fail(ctx, e, "batch class enable");
+  cur = mask;
   if (full) {
     e = hipGraphExecMemcpyNodeSetParams1D(x_full, cpy_full, d_buf, h_buf, bytes,
                                           hipMemcpyHostToDevice);

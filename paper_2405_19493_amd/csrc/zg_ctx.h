@@ -19,27 +19,33 @@ struct HandleInfo {
   bool open;
 };
 
-// A validated batch ready for upload: only requests with n > 0, in order.
+// A validated batch ready for upload: only requests with n > 0, in order,
+// and the workgroup tiles of each work class.
 struct BatchPlan {
   std::vector<DevRequest> reqs;
   std::vector<uint32_t> index;   // position of each planned request in the caller's array
-  uint64_t total_tiles = 0;
+  std::vector<uint64_t> items;   // request << 32 | tile, grouped by class
+  uint32_t cls_off[BATCH_CLASSES] = {};
+  uint32_t cls_cnt[BATCH_CLASSES] = {};
   uint64_t total_elems = 0;
 };
 
 struct BatchSlot {
-  void *h_buf = nullptr;   // pinned staging: BatchHeader + DevRequest[cap]
+  void *h_buf = nullptr;   // pinned staging: BatchHeader, DevRequest[nreq], items[n_items]
   void *d_buf = nullptr;
   size_t cap = 0;
+  size_t item_cap = 0;
   hipGraph_t g_full = nullptr, g_prep = nullptr, g_run = nullptr;
   hipGraphExec_t x_full = nullptr, x_prep = nullptr, x_run = nullptr;
   hipGraphNode_t cpy_full = nullptr, cpy_prep = nullptr;
+  hipGraphNode_t cls_full[BATCH_CLASSES] = {}, cls_run[BATCH_CLASSES] = {};
+  uint32_t mask_full = 0xFFu, mask_run = 0xFFu;   // class nodes currently enabled
   hipEvent_t done = nullptr;   // recorded after the last use of the staging buffer
   bool busy = false;
   bool recorded = false;
 
   DevRequest *d_reqs() const { return (DevRequest *)((char *)d_buf + sizeof(BatchHeader)); }
-  zg_status ensure(struct ::zg_ctx *ctx, size_t nreq);
+  zg_status ensure(struct ::zg_ctx *ctx, size_t nreq, size_t nitems);
   zg_status build_graphs(struct ::zg_ctx *ctx);
   void invalidate_graphs();
   void release();

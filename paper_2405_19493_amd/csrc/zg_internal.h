@@ -69,29 +69,42 @@ struct Job {
 
 // A batch request as the device sees it (host fills all but `first`,
 // which the reserve kernel resolves from the counters when handle >= 0).
+// The request is split into workgroup tiles of `tile` elements per wave; its
+// completion word is written once the whole batch has run.
 struct DevRequest {
   Job job;
   uint64_t off;          // counter offset of this request among earlier
                          // requests of the same handle in the batch
-  uint64_t tile0;        // first global tile index of this request
   int32_t handle;
   uint32_t last_of_handle;   // 1: advance the counter by off + n after the batch
   uint64_t limit;        // index window of the kind (first + n must stay <= limit)
   uint32_t *done_flag;   // host-visible completion word (may be null)
   uint64_t *first_host;  // host-visible copy of the resolved first index (may be null)
   uint32_t done_value;
-  uint32_t tiles;        // number of tiles of this request
+  uint32_t tiles;        // workgroup tiles of this request
   uint32_t status;       // 0 ok, ZG_FLAG_RANGE when skipped
-  uint32_t remaining;    // tiles not yet finished (counted down on the device)
-  uint32_t tile;         // elements per tile
+  uint32_t pad;
+  uint32_t tile;         // elements per wave of a workgroup tile
   uint32_t head;         // elements before the first 16-byte aligned one
 };
 
-// Batch header, uploaded with the requests.
+// Work classes of a batch: op (ZIG64, ZIG32, MUTATE, POLAR) x uniform kind
+// (SplitMix64, LCG48); each runs in its own specialised kernel.
+constexpr int BATCH_CLASSES = 8;
+__host__ __device__ constexpr int batch_class(uint32_t op, uint32_t kind) {
+  return 2 * (op == OP_ZIG64 ? 0 : op == OP_ZIG32 ? 1 : op == OP_MUTATE ? 2 : 3) +
+         (kind == ZG_JAVA_LCG48 ? 1 : 0);
+}
+
+// Batch header, uploaded with the requests and the work items (one 64-bit
+// item per workgroup tile: request index << 32 | tile index, grouped by class).
 struct BatchHeader {
   uint32_t nreq;
   uint32_t dmax;
-  uint64_t total_tiles;
+  uint32_t n_items;
+  uint32_t items_off;   // byte offset of the items from the header
+  uint32_t cls_off[BATCH_CLASSES];
+  uint32_t cls_cnt[BATCH_CLASSES];
   uint64_t pad[6];
 };
 
@@ -104,8 +117,10 @@ hipError_t launch_words(uint64_t *out, uint64_t n, const DevTables *T, uint32_t 
 hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, uint8_t *cls,
                          double *x, hipStream_t stream);
 const void *kernel_reserve();
-const void *kernel_batch();
-size_t batch_lds_bytes(uint32_t waves);
+const void *kernel_complete();
+// The kernel of a work class, and its dynamic LDS for `waves` waves.
+const void *kernel_batch_class(int cls);
+size_t batch_class_lds_bytes(int cls, uint32_t waves);
 
 zg_status build_table(zg_table_view *t);
 void build_lcg_tables(LcgTables *L);

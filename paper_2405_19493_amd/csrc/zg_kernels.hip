@@ -4,12 +4,17 @@
 // ziggurat of Marsaglia-Tsang and Leong, as in GSL):
 //   keyed uniform word -> decode (layer, sign, j) -> fast accept j < k[i]
 //   with x = j w[i] (one multiply and one compare per lane) -> coalesced
-//   128-bit stores.  Lanes that fail the fast test are compacted with a wave
-//   ballot and a lane prefix count into a per-wave LDS queue; the queue is
-//   drained 64 entries at a time, each lane running the wedge / tail / retry
-//   loop for one queued variate, so the rare slow path does not diverge the
-//   fast one.  Every variate is a pure function of its index, so the launch
-//   shape, the queue order and the batch layout never change the bits.
+//   128-bit stores.  Lanes that fail the fast test are compacted with wave
+//   ballots and lane prefix counts into one LDS queue per workgroup; the
+//   queue is drained 64 entries at a time, each lane running the wedge /
+//   tail / retry loop of one queued variate, so the rare slow path does not
+//   diverge the fast one.  Every variate is a pure function of its index, so
+//   the launch shape, the queue order and the batch layout never change the
+//   bits.
+//
+// Also here: the polar method (Section 1; Java's nextGaussian), the uniform
+// word export, the per-word decision probe, and the batch kernels (counter
+// reservation, one specialised kernel per work class, completion words).
 //
 // Build with -ffp-contract=off: the fast-path product and the wedge
 // y = y[i-1] + U dy[i] must be rounded exactly as written.
@@ -24,7 +29,7 @@ namespace zg {
 #define DEV __device__ __forceinline__
 
 constexpr uint64_t MASK53 = (1ull << 53) - 1;
-constexpr int QCAP = 1088;             // main queue entries per wave (>= 63 + one flush)
+constexpr int QCAP = 1088;             // polar queue entries per wave (>= 63 + 2 per lane of a step)
 
 // ------------------------------------------------------------ uniform words
 
@@ -96,69 +101,6 @@ DEV uint64_t wordk(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, ui
   return sm64_word(seed, s, v, d);
 }
 
-struct Step {
-  int status;        // 1 accepted, 0 rejected, -1 draw budget exhausted
-  double x;
-  uint32_t next_d;
-};
-
-// Wedge (i >= 1) or tail (i == 0) test of the attempt at draw d whose first
-// word gave candidate x in layer i.
-template <int KIND>
-DEV Step slow_step(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, uint32_t d,
-                   uint32_t dmax, uint32_t i, double x) {
-  if (i == 0) {
-    if (d + 2 >= dmax) return {-1, 0.0, d};
-    double u1 = u53p(wordk<KIND>(T, seed, s, v, d + 1));
-    double u2 = u53(wordk<KIND>(T, seed, s, v, d + 2));
-    double r = T->r;
-    double a = -log(u1) / r;
-    double xt = r + a;
-    return {u2 < exp(-0.5 * (a * a)) ? 1 : 0, xt, d + 3};
-  }
-  if (d + 1 >= dmax) return {-1, 0.0, d};
-  double u = u53(wordk<KIND>(T, seed, s, v, d + 1));
-  double y = T->y[i - 1] + u * T->dy[i];
-  return {y < exp(-0.5 * (x * x)) ? 1 : 0, x, d + 2};
-}
-
-// One full FP64 attempt at draw d (signed result on acceptance).
-template <int KIND>
-DEV Step attempt64(const DevTables *T, const Fast64 *fast, uint64_t seed, uint32_t s, uint64_t v,
-                   uint32_t d, uint32_t dmax) {
-  if (d >= dmax) return {-1, 0.0, d};
-  uint64_t W = wordk<KIND>(T, seed, s, v, d);
-  uint32_t i = (uint32_t)(W >> 57);
-  Fast64 f = fast[i];
-  uint64_t j = (W >> 3) & MASK53;
-  double x = to_f64(j) * f.w;
-  Step st;
-  if (j < f.k)
-    st = {1, x, d};
-  else
-    st = slow_step<KIND>(T, seed, s, v, d, dmax, i, x);
-  if (st.status == 1) st.x = flip(st.x, (W >> 56) & 1);
-  return st;
-}
-
-// Fast test only of the attempt at draw d: 1 accepted, 0 not fast, -1 budget.
-template <int KIND>
-DEV Step fast_only64(const DevTables *T, const Fast64 *fast, uint64_t seed, uint32_t s,
-                     uint64_t v, uint32_t d, uint32_t dmax) {
-  if (d >= dmax) return {-1, 0.0, d};
-  uint64_t W = wordk<KIND>(T, seed, s, v, d);
-  Fast64 f = fast[(uint32_t)(W >> 57)];
-  uint64_t j = (W >> 3) & MASK53;
-  if (j < f.k) return {1, flip(to_f64(j) * f.w, (W >> 56) & 1), d};
-  return {0, 0.0, d};
-}
-
-struct Step32 {
-  int status;
-  float x;
-  uint32_t next_d;
-};
-
 // The 32-bit attempt word of FP32 mode.
 template <int KIND>
 DEV uint32_t word32(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
@@ -167,39 +109,6 @@ DEV uint32_t word32(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, u
     return (v & 1) ? (uint32_t)W : (uint32_t)(W >> 32);
   }
   return (uint32_t)(wordk<KIND>(T, seed, s, v, d) >> 32);
-}
-
-template <int KIND>
-DEV Step32 fast_only32(const DevTables *T, const Fast32 *fast, uint64_t seed, uint32_t s,
-                       uint64_t v, uint32_t d, uint32_t dmax) {
-  if (d >= dmax) return {-1, 0.f, d};
-  uint32_t u = word32<KIND>(T, seed, s, v, d);
-  Fast32 f = fast[u >> 25];
-  uint32_t j = u & 0xFFFFFFu;
-  if (j < f.k) {
-    float xf = (float)j * f.w;
-    return {1, ((u >> 24) & 1) ? -xf : xf, d};
-  }
-  return {0, 0.f, d};
-}
-
-template <int KIND>
-DEV Step32 attempt32(const DevTables *T, const Fast32 *fast, uint64_t seed, uint32_t s, uint64_t v,
-                     uint32_t d, uint32_t dmax) {
-  if (d >= dmax) return {-1, 0.f, d};
-  uint32_t u = word32<KIND>(T, seed, s, v, d);
-  uint32_t i = u >> 25;
-  uint32_t neg = (u >> 24) & 1;
-  uint32_t j = u & 0xFFFFFFu;
-  Fast32 f = fast[i];
-  if (j < f.k) {
-    float xf = (float)j * f.w;
-    return {1, neg ? -xf : xf, d};
-  }
-  double x = (double)j * T->w24d[i];
-  Step st = slow_step<KIND>(T, seed, s, v, d, dmax, i, x);
-  float xf = (float)(neg ? -st.x : st.x);
-  return {st.status, xf, st.next_d};
 }
 
 struct PolarStep {
@@ -281,14 +190,6 @@ DEV void split(const Job &J, uint64_t e, uint32_t &s, uint64_t &v) {
   v = J.first + (uint64_t)r;
 }
 
-struct Ctx {
-  const DevTables *T;
-  const Fast64 *f64;   // LDS
-  const Fast32 *f32;   // LDS
-  uint32_t dmax;
-  uint32_t *flags;
-};
-
 DEV void raise_flag(uint32_t *flags, uint32_t bit) { atomicOr(flags, bit); }
 
 // Sign from bit 24 of the word's high dword, applied to the double's high dword.
@@ -299,204 +200,29 @@ DEV double flip_hi(double x, uint32_t whi) {
   return __hiloint2double(__double2hiint(x) ^ (int)((whi << 7) & 0x80000000u), __double2loint(x));
 }
 
-// ------------------------------------------------------------ queue drain
+// ------------------------------------------------------------ polar path
 //
-// Each wave owns two LDS lists of 32-bit entries (offset from the tile base,
-// draw index, flags): the main queue of variates whose attempt failed the fast
-// test, and a short list of attempts that landed in the base layer beyond r
-// (the tail step, with a log and an exp, is much longer than the wedge step,
-// so tails are run together once per tile instead of in most rounds).
+// Each wave owns an LDS queue of 32-bit entries (element offset from the
+// tile base, draw index, flags): pairs whose first attempt was rejected, and
+// elements whose pair straddles a stream boundary or the tile edge.  The
+// queue is drained 64 entries per round, one attempt per lane per round.
 
-constexpr uint32_t TCAP = 128;   // tail list entries per wave
-
-struct Queues {
-  uint32_t *q;    // main queue, QCAP entries
-  uint32_t *t;    // tail list, TCAP entries
-  uint32_t qn;    // wave-uniform counts
-  uint32_t tn;
+// Context of the polar path.
+struct PolarCtx {
+  const DevTables *T;
+  uint32_t dmax;
+  uint32_t *flags;
 };
 
-// Decoded first word of an attempt at draw d.
-struct Att {
-  uint32_t cls;    // 0 fast, 1 wedge, 2 tail
-  uint32_t i;
-  uint32_t neg;
-  double x;        // candidate (FP64; FP32 mode: j * w24d[i], slow path only)
-  float xf;        // FP32 mode: fast-path value (unsigned)
+struct Queue {
+  uint32_t *q;    // QCAP entries
+  uint32_t qn;    // wave-uniform count
 };
-
-template <int OP, int KIND>
-DEV Att decode_attempt(const Ctx &C, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
-  Att a;
-  if (OP == OP_ZIG32) {
-    const uint32_t u = word32<KIND>(C.T, seed, s, v, d);
-    a.i = u >> 25;
-    a.neg = (u >> 24) & 1;
-    const uint32_t j = u & 0xFFFFFFu;
-    const Fast32 f = C.f32[a.i];
-    a.xf = (float)j * f.w;
-    a.x = (double)j * C.T->w24d[a.i];
-    a.cls = j < f.k ? 0u : (a.i ? 1u : 2u);
-  } else {
-    const uint64_t W = wordk<KIND>(C.T, seed, s, v, d);
-    a.i = (uint32_t)(W >> 57);
-    a.neg = (uint32_t)(W >> 56) & 1;
-    const uint64_t j = (W >> 3) & MASK53;
-    const Fast64 f = C.f64[a.i];
-    a.x = to_f64(j) * f.w;
-    a.xf = 0.f;
-    a.cls = j < f.k ? 0u : (a.i ? 1u : 2u);
-  }
-  return a;
-}
-
-// Writes an accepted value (x is the unsigned FP64 candidate, or for an FP32
-// fast path, xf) or the budget NaN.
-template <int OP>
-DEV void finish(const Job &J, const Ctx &C, uint64_t e, int status, const Att &a, double x) {
-  if (status < 0) raise_flag(C.flags, ZG_FLAG_BUDGET);
-  if (OP == OP_ZIG32) {
-    float r;
-    if (status < 0)
-      r = nan32();
-    else if (a.cls == 0)
-      r = a.neg ? -a.xf : a.xf;
-    else
-      r = (float)(a.neg ? -x : x);
-    ((float *)J.out)[e] = r;
-  } else {
-    const double z = status < 0 ? nan64() : (a.neg ? -x : x);
-    double *out = (double *)J.out;
-    if (OP == OP_MUTATE)
-      out[e] = out[e] + J.sigma * z;
-    else
-      out[e] = z;
-  }
-}
-
-// Where a variate goes after a rejected attempt: its next attempt at draw d2
-// gets its fast test now; fast -> done, else it is queued (wedge) or listed
-// (tail) with draw d2.
-template <int OP, int KIND>
-DEV void next_attempt(const Job &J, const Ctx &C, uint64_t e, uint32_t s, uint64_t v, uint32_t d2,
-                      uint32_t off, bool &to_q, bool &to_t, uint32_t &ent) {
-  if (d2 >= C.dmax) {
-    Att none{};
-    finish<OP>(J, C, e, -1, none, 0.0);
-    return;
-  }
-  const Att a = decode_attempt<OP, KIND>(C, J.seed, s, v, d2);
-  if (a.cls == 0) {
-    finish<OP>(J, C, e, 1, a, a.x);
-  } else {
-    ent = qent(off, d2, 0);
-    to_q = a.cls == 1;
-    to_t = a.cls == 2;
-  }
-}
-
-// One round over up to 64 main-queue entries: wedge steps.
-template <int OP, int KIND>
-DEV void wedge_round(const Job &J, const Ctx &C, Queues &Q, uint64_t e_base) {
-  const uint32_t lane = lane_id();
-  const uint32_t m = Q.qn < 64 ? Q.qn : 64;
-  const bool has = lane < m;
-  const uint32_t ent = has ? Q.q[Q.qn - m + lane] : 0u;
-  Q.qn = uni(Q.qn - m);
-  __builtin_amdgcn_wave_barrier();
-  bool to_q = false, to_t = false;
-  uint32_t nent = 0;
-  if (has) {
-    const uint32_t off = ent & OFF_MASK;
-    const uint32_t d = (ent >> 21) & 255u;
-    const uint64_t e = e_base + off;
-    uint32_t s;
-    uint64_t v;
-    split(J, e, s, v);
-    const Att a = d < C.dmax ? decode_attempt<OP, KIND>(C, J.seed, s, v, d) : Att{};
-    if (d >= C.dmax) {
-      finish<OP>(J, C, e, -1, a, 0.0);
-    } else if (a.cls == 0) {
-      finish<OP>(J, C, e, 1, a, a.x);
-    } else if (a.cls == 2) {
-      to_t = true;   // defer the tail step
-      nent = qent(off, d, 0);
-    } else if (d + 1 >= C.dmax) {
-      finish<OP>(J, C, e, -1, a, 0.0);
-    } else {
-      const double u = u53(wordk<KIND>(C.T, J.seed, s, v, d + 1));
-      const double y = C.T->y[a.i - 1] + u * C.T->dy[a.i];
-      if (y < exp(-0.5 * (a.x * a.x)))
-        finish<OP>(J, C, e, 1, a, a.x);
-      else
-        next_attempt<OP, KIND>(J, C, e, s, v, d + 2, off, to_q, to_t, nent);
-    }
-  }
-  qpush2(Q.q, Q.qn, to_q, nent, false, 0u);
-  qpush2(Q.t, Q.tn, to_t, nent, false, 0u);
-}
-
-// One round over up to 64 tail-list entries: tail steps.
-template <int OP, int KIND>
-DEV void tail_round(const Job &J, const Ctx &C, Queues &Q, uint64_t e_base) {
-  const uint32_t lane = lane_id();
-  const uint32_t m = Q.tn < 64 ? Q.tn : 64;
-  const bool has = lane < m;
-  const uint32_t ent = has ? Q.t[Q.tn - m + lane] : 0u;
-  Q.tn = uni(Q.tn - m);
-  __builtin_amdgcn_wave_barrier();
-  bool to_q = false, to_t = false;
-  uint32_t nent = 0;
-  if (has) {
-    const uint32_t off = ent & OFF_MASK;
-    const uint32_t d = (ent >> 21) & 255u;
-    const uint64_t e = e_base + off;
-    uint32_t s;
-    uint64_t v;
-    split(J, e, s, v);
-    Att a = decode_attempt<OP, KIND>(C, J.seed, s, v, d);   // sign of the attempt
-    if (d + 2 >= C.dmax) {
-      finish<OP>(J, C, e, -1, a, 0.0);
-    } else {
-      const double u1 = u53p(wordk<KIND>(C.T, J.seed, s, v, d + 1));
-      const double u2 = u53(wordk<KIND>(C.T, J.seed, s, v, d + 2));
-      const double r = C.T->r;
-      const double t = -log(u1) / r;
-      if (u2 < exp(-0.5 * (t * t))) {
-        a.cls = 2;
-        finish<OP>(J, C, e, 1, a, r + t);
-      } else {
-        next_attempt<OP, KIND>(J, C, e, s, v, d + 3, off, to_q, to_t, nent);
-      }
-    }
-  }
-  qpush2(Q.q, Q.qn, to_q, nent, false, 0u);
-  qpush2(Q.t, Q.tn, to_t, nent, false, 0u);
-}
-
-// Drains the main queue down to `keep` entries (full rounds); the tail list
-// is run when it could overflow, or completely when `final`.  Rounds end:
-// every requeue advances a variate's draw index by at least 2.
-template <int OP, int KIND>
-DEV void drain(const Job &J, const Ctx &C, Queues &Q, uint32_t keep, bool final,
-               uint64_t e_base) {
-  if (Q.qn > keep || (final && Q.tn > 0) || Q.tn > TCAP - 64)
-    __threadfence_block();   // placeholders are written before any patch
-  for (;;) {
-    while (Q.qn > keep) {
-      wedge_round<OP, KIND>(J, C, Q, e_base);
-      if (Q.tn > TCAP - 64) tail_round<OP, KIND>(J, C, Q, e_base);
-    }
-    if (!final || Q.tn == 0) break;
-    tail_round<OP, KIND>(J, C, Q, e_base);
-  }
-}
 
 // Polar drain: one attempt per round, rejected pairs requeued.
 template <int KIND>
-DEV void drain_polar(const Job &J, const Ctx &C, Queues &Q, uint32_t keep, uint64_t e_base) {
+DEV void drain_polar(const Job &J, const PolarCtx &C, Queue &Q, uint32_t keep, uint64_t e_base) {
   const uint32_t lane = lane_id();
-  if (Q.qn > keep) __threadfence_block();
   while (Q.qn > keep) {
     const uint32_t m = Q.qn < 64 ? Q.qn : 64;
     const bool has = lane < m;
@@ -533,34 +259,6 @@ DEV void drain_polar(const Job &J, const Ctx &C, Queues &Q, uint32_t keep, uint6
     }
     qpush2(Q.q, Q.qn, pend, requeue, false, 0u);
   }
-}
-
-// Flushes a lane's slow-element bits (bit b = element OFFS[b & 3] + (b >> 2)
-// steps after the lane's group base) into the main queue: a wave-wide
-// exclusive prefix of the popcounts from five ballots, then each lane writes
-// its entries.  Wave-uniform call.
-template <uint32_t STEP, uint32_t CH, bool PAIRS>
-DEV void flush_bits(Queues &Q, uint32_t bits, uint32_t lane_base) {
-  const uint32_t p = __builtin_popcount(bits);   // 0..16
-  const uint64_t B0 = __builtin_amdgcn_ballot_w64((p & 1) != 0);
-  const uint64_t B1 = __builtin_amdgcn_ballot_w64((p & 2) != 0);
-  const uint64_t B2 = __builtin_amdgcn_ballot_w64((p & 4) != 0);
-  const uint64_t B3 = __builtin_amdgcn_ballot_w64((p & 8) != 0);
-  const uint64_t B4 = __builtin_amdgcn_ballot_w64((p & 16) != 0);
-  if ((B0 | B1 | B2 | B3 | B4) == 0) return;
-  uint32_t pos = Q.qn + prefix_below(B0) + 2 * prefix_below(B1) + 4 * prefix_below(B2) +
-                 8 * prefix_below(B3) + 16 * prefix_below(B4);
-  while (bits) {
-    const uint32_t b = __builtin_ctz(bits);
-    bits &= bits - 1;
-    const uint32_t t = b & 3;
-    const uint32_t o = PAIRS ? ((t >> 1) * CH + (t & 1)) : t;
-    Q.q[pos++] = lane_base + (b >> 2) * STEP + o;
-  }
-  Q.qn = uni(Q.qn + (uint32_t)__popcll(B0) + 2 * (uint32_t)__popcll(B1) +
-             4 * (uint32_t)__popcll(B2) + 8 * (uint32_t)__popcll(B3) +
-             16 * (uint32_t)__popcll(B4));
-  __builtin_amdgcn_wave_barrier();
 }
 
 // --------------------------------------------------------- lane constants
@@ -616,115 +314,9 @@ DEV double fast64(const Fast64 *tab, uint64_t W, bool &fast) {
   return flip_hi(to_f64(j) * f.w, hi);
 }
 
-// Per-tile loop state of the ziggurat kernels.
-struct TileState {
-  uint64_t k, r;        // stream position of the step (wave-uniform)
-  uint32_t bits, sub;   // slow-element bits of the current group, step in group
-  uint32_t lane_base;   // queue offset of the lane's first element in the group
-};
-
-// One ziggurat step: 4 elements per lane.  FULL: the whole step lies inside
-// the tile (no masks).  Returns the lane's 4 slow bits.
-template <int OP, int KIND, bool FULL>
-DEV uint32_t zig_step(const Job &J, const Ctx &C, const LaneConst &LC, uint64_t ec, uint64_t e_end,
-                      uint32_t s, uint64_t vc) {
-  constexpr uint32_t E = (OP == OP_ZIG32) ? 4 : 2;
-  constexpr uint32_t CH = 64 * E;
-  constexpr bool LCG = KIND == ZG_JAVA_LCG48;
-  const uint32_t lane = lane_id();
-  const uint64_t e0 = ec + (uint64_t)E * lane;
-  const uint64_t seed = J.seed;
-  uint32_t b4 = 0;
-  if (OP == OP_ZIG64 || OP == OP_MUTATE) {
-    uint64_t W[4];
-    if (LCG) {
-      uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
-      W[0] = lcg_word_from(aff(LC.a[0], Sc));
-      W[1] = lcg_word_from(aff(LC.a[1], Sc));
-      Sc = aff(C.T->lcg.jump[1][1], Sc);   // 256 steps = the next 128-element chunk
-      W[2] = lcg_word_from(aff(LC.a[0], Sc));
-      W[3] = lcg_word_from(aff(LC.a[1], Sc));
-    } else {
-      const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + vc);
-      W[0] = mix64(zc + LC.g[0]);
-      W[1] = mix64(zc + LC.g[1]);
-      W[2] = mix64(zc + GAMMA * (uint64_t)CH + LC.g[0]);
-      W[3] = mix64(zc + GAMMA * (uint64_t)CH + LC.g[1]);
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < 2; ++u) {
-      const uint64_t ea = e0 + u * CH;
-      const bool ok0 = FULL || ea < e_end, ok1 = FULL || ea + 1 < e_end;
-      bool fast0, fast1;
-      double x0 = fast64(C.f64, W[2 * u], fast0);
-      double x1 = fast64(C.f64, W[2 * u + 1], fast1);
-      double *out = (double *)J.out + ea;
-      if (OP == OP_MUTATE) {
-        if (FULL || (ok0 && ok1)) {
-          const double2 old = *(const double2 *)out;
-          x0 = fast0 ? old.x + J.sigma * x0 : old.x;
-          x1 = fast1 ? old.y + J.sigma * x1 : old.y;
-        } else if (ok0) {
-          const double old = out[0];
-          x0 = fast0 ? old + J.sigma * x0 : old;
-        }
-      }
-      if (FULL || (ok0 && ok1)) {
-        *(double2 *)out = make_double2(x0, x1);
-      } else if (ok0) {
-        out[0] = x0;
-      }
-      b4 |= ((ok0 && !fast0) ? 1u : 0u) << (2 * u);
-      b4 |= ((ok1 && !fast1) ? 2u : 0u) << (2 * u);
-    }
-  } else {  // OP_ZIG32
-    uint32_t uw[4];
-    if (!LCG) {
-      const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + (vc >> 1));
-      const uint64_t Wa = mix64(zc + LC.g[0]), Wb = mix64(zc + LC.g[1]);
-      if ((vc & 1) == 0) {
-        uw[0] = (uint32_t)(Wa >> 32);
-        uw[1] = (uint32_t)Wa;
-        uw[2] = (uint32_t)(Wb >> 32);
-        uw[3] = (uint32_t)Wb;
-      } else {
-        const uint64_t Wc = mix64(zc + LC.g[2]);
-        uw[0] = (uint32_t)Wa;
-        uw[1] = (uint32_t)(Wb >> 32);
-        uw[2] = (uint32_t)Wb;
-        uw[3] = (uint32_t)(Wc >> 32);
-      }
-    } else {
-      const uint64_t Sc = lcg_jump(&C.T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) uw[t] = (uint32_t)(lcg_word_from(aff(LC.a[t], Sc)) >> 32);
-    }
-    float x[4];
-    bool ok[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const Fast32 f = C.f32[uw[t] >> 25];
-      const uint32_t j = uw[t] & 0xFFFFFFu;
-      ok[t] = FULL || e0 + t < e_end;
-      const float xf = (float)j * f.w;
-      x[t] = __int_as_float(__float_as_int(xf) ^ (int)((uw[t] << 7) & 0x80000000u));
-      b4 |= ((ok[t] && !(j < f.k)) ? 1u : 0u) << t;
-    }
-    float *out = (float *)J.out + e0;
-    if (FULL || ok[3]) {
-      *(float4 *)out = make_float4(x[0], x[1], x[2], x[3]);   // slow ones: placeholders
-    } else {
-#pragma unroll
-      for (int t = 0; t < 3; ++t)
-        if (ok[t]) out[t] = x[t];
-    }
-  }
-  return b4;
-}
-
 // One polar step: a pair per lane (2 elements).
 template <int KIND>
-DEV void polar_step(const Job &J, const Ctx &C, const LaneConst &LC, Queues &Q, uint64_t ec,
+DEV void polar_step(const Job &J, const PolarCtx &C, const LaneConst &LC, Queue &Q, uint64_t ec,
                     uint64_t e_end, uint32_t s, uint64_t vc, bool clean, uint32_t o0) {
   constexpr bool LCG = KIND == ZG_JAVA_LCG48;
   const uint32_t lane = lane_id();
@@ -761,103 +353,45 @@ DEV void polar_step(const Job &J, const Ctx &C, const LaneConst &LC, Queues &Q, 
   qpush2(Q.q, Q.qn, push_a, ent_a, push_b, ent_b);
 }
 
-// Processes elements [e_begin, e_end) of job J with one wave, then drains the
-// wave's queues completely.  e_begin is 16-byte aligned in the output and
-// e_end - e_begin is arbitrary.  Elements [0, head) of the job (before the
-// aligned body) are queued first when `with_head`.
-//
-// Ziggurat steps: every lane handles 4 elements per step (two 128-element
-// chunks of FP64 pairs, or one 256-element chunk of FP32 quads), stores all of
-// them with 128-bit stores (a slow element gets a placeholder that the drain
-// overwrites after a fence; for mutation the placeholder is the old value) and
-// records its slow elements in a bit mask that is flushed into the queue every
-// 4 steps.  Steps that straddle a stream boundary mark all their elements slow:
-// the drain keys every element by itself, so the hot loop never divides.
-template <int OP, int KIND>
-DEV void process_tile(const Job &J, const Ctx &C, const LaneConst &LC, uint32_t *lds,
-                      uint64_t e_begin, uint64_t e_end, uint32_t head, bool with_head) {
-  constexpr uint32_t E = (OP == OP_ZIG32) ? 4 : 2;
-  constexpr uint32_t CH = 64 * E;
-  constexpr uint32_t U = (OP == OP_ZIG64 || OP == OP_MUTATE) ? 2 : 1;   // chunks per step
-  constexpr uint32_t STEP = CH * U;
-  constexpr uint32_t GROUP = 4;                                         // steps per flush
-  constexpr bool ZIG = OP != OP_POLAR;
+// Polar method over elements [e_begin, e_end) of job J with one wave, then
+// a full drain.  e_begin is 16-byte aligned in the output; elements [0, head)
+// of the job (before the aligned body) are queued first when `with_head`.
+// Every lane takes one pair per step; a pair is attempted at once when it
+// lies inside one stream and inside the tile, otherwise its elements are
+// queued one by one (each keyed by itself).
+template <int KIND>
+DEV void polar_tile(const Job &J, const PolarCtx &C, const LaneConst &LC, uint32_t *lds,
+                    uint64_t e_begin, uint64_t e_end, uint32_t head, bool with_head) {
+  constexpr uint32_t STEP = 128;   // elements per step (a pair per lane)
   const uint32_t lane = lane_id();
   e_begin = uni64(e_begin);
   e_end = uni64(e_end);
   // queue offsets are relative to e_base; the head elements precede e_begin
   const uint64_t e_base = with_head ? 0 : e_begin;
-  Queues Q{lds, lds + QCAP, 0u, 0u};
+  Queue Q{lds, 0u};
   if (with_head && head) qpush2(Q.q, Q.qn, lane < head, qent(lane, 0, 0), false, 0u);
   const bool multi = J.n_streams != 1;
-  TileState S;
-  S.k = 0;
-  S.r = e_begin;
+  uint64_t k = 0, r = e_begin;
   if (multi) {
-    S.k = uni64(e_begin / J.n_per);
-    S.r = uni64(e_begin - S.k * J.n_per);
+    k = uni64(e_begin / J.n_per);
+    r = uni64(e_begin - k * J.n_per);
   }
-  S.bits = 0;
-  S.sub = 0;
-  S.lane_base = (uint32_t)(e_begin - e_base) + E * lane;
+  uint32_t o0 = (uint32_t)(e_begin - e_base) + 2 * lane;
   for (uint64_t ec = e_begin; ec < e_end; ec += STEP) {
-    const bool clean = !multi || S.r + STEP <= J.n_per;
-    const uint32_t s = uni(J.s0 + (uint32_t)S.k);
-    const uint64_t vc = uni64(J.first + S.r);
-    if (ZIG) {
-      uint32_t b4;
-      if (!clean) {
-        // straddles a stream boundary: every element goes to the drain
-        const uint64_t e0 = ec + (uint64_t)E * lane;
-        b4 = 0;
-#pragma unroll
-        for (uint32_t t = 0; t < 4; ++t) {
-          const uint64_t et = e0 + (U == 2 ? (t >> 1) * CH + (t & 1) : t);
-          b4 |= (et < e_end ? 1u : 0u) << t;
-        }
-      } else if (ec + STEP <= e_end) {
-        b4 = zig_step<OP, KIND, true>(J, C, LC, ec, e_end, s, vc);
-      } else {
-        b4 = zig_step<OP, KIND, false>(J, C, LC, ec, e_end, s, vc);
-      }
-      S.bits |= b4 << (4 * S.sub);
-      if (++S.sub == GROUP) {
-        flush_bits<STEP, CH, U == 2>(Q, S.bits, S.lane_base);
-        S.bits = 0;
-        S.sub = 0;
-        S.lane_base += GROUP * STEP;
-        if (Q.qn > (uint32_t)QCAP - GROUP * STEP) drain<OP, KIND>(J, C, Q, 63, false, e_base);
-      }
-    } else {
-      polar_step<KIND>(J, C, LC, Q, ec, e_end, s, vc, clean, S.lane_base + S.sub * STEP);
-      if (++S.sub == GROUP) {
-        S.sub = 0;
-        S.lane_base += GROUP * STEP;
-      }
-      if (Q.qn > (uint32_t)QCAP - STEP) drain_polar<KIND>(J, C, Q, 63, e_base);
-    }
-    S.r += STEP;
+    const bool clean = !multi || r + STEP <= J.n_per;
+    const uint32_t s = uni(J.s0 + (uint32_t)k);
+    const uint64_t vc = uni64(J.first + r);
+    polar_step<KIND>(J, C, LC, Q, ec, e_end, s, vc, clean, o0);
+    o0 += STEP;
+    if (Q.qn > (uint32_t)QCAP - STEP) drain_polar<KIND>(J, C, Q, 63, e_base);
+    r += STEP;
     if (multi)
-      while (S.r >= J.n_per) {
-        S.r -= J.n_per;
-        ++S.k;
+      while (r >= J.n_per) {
+        r -= J.n_per;
+        ++k;
       }
   }
-  if (ZIG) {
-    if (S.sub) flush_bits<STEP, CH, U == 2>(Q, S.bits, S.lane_base);
-    drain<OP, KIND>(J, C, Q, 0, true, e_base);
-  } else {
-    drain_polar<KIND>(J, C, Q, 0, e_base);
-  }
-}
-
-// Loads the fast tables into LDS (whole block; ends with a barrier).
-DEV void load_fast(const DevTables *T, Fast64 *f64, Fast32 *f32, bool need64, bool need32) {
-  for (uint32_t i = threadIdx.x; i < ZG_LAYERS; i += blockDim.x) {
-    if (need64) f64[i] = T->fast64[i];
-    if (need32) f32[i] = T->fast32[i];
-  }
-  __syncthreads();
+  drain_polar<KIND>(J, C, Q, 0, e_base);
 }
 
 // ------------------------------------------------ block-pooled ziggurat fill
@@ -1260,25 +794,22 @@ DEV uint64_t tile_pass(const Job &J, BlockLds &L, const DevTables *T, const Lane
   return stop;
 }
 
+// One workgroup tile [b0, b1) of job J (wave w: [b0 + w tile, + tile)):
+// streaming pass, one barrier, pooled drain, overflow pass; `head` elements
+// before b0 (the unaligned start of the job) are resolved too when non-zero.
+// The tables in L are loaded; the caller separates consecutive calls with a
+// barrier (the queue count is reset here, before the first barrier).
 template <int OP, int KIND>
-__global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict__ T,
-                                              uint32_t dmax, uint32_t *flags, uint32_t tile,
-                                              uint32_t head, uint32_t qcap) {
-  __shared__ BlockLds L;
-  load_tabs<OP>(T, L.t);
-  if (threadIdx.x == 0) L.cnt = 0;
-  __syncthreads();
+DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
+                   const LaneConst &LC, double r, uint32_t dmax, uint32_t tile, uint64_t b0,
+                   uint64_t b1, uint32_t head, uint32_t qcap, bool &budget) {
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wave = uni(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
-  const double r = T->r;
-  bool budget = false;
-  const uint64_t bt = (uint64_t)tile * nw;
-  const uint64_t b0 = uni64((uint64_t)blockIdx.x * bt + head);
-  const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
+  if (threadIdx.x == 0) L.cnt = 0;
+  __syncthreads();
   const uint64_t ew = uni64(b0 + (uint64_t)wave * tile < b1 ? b0 + (uint64_t)wave * tile : b1);
   const uint64_t ee = uni64(ew + tile < b1 ? ew + tile : b1);
-  const LaneConst LC = lane_constants<OP, KIND>(T);
   uint64_t stop = ee, stored = ee;
   if (ew < ee) stop = tile_pass<OP, KIND>(J, L, T, LC, b0, ew, ee, qcap, stored);
   __syncthreads();   // placeholders before patches; the queue is complete
@@ -1304,36 +835,50 @@ __global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict
     if (e < stored && first_fast<OP, KIND>(J, L.t, T, se, ve)) continue;
     patch_store<OP>(J, e, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
   }
-  // the elements before the first aligned one (block 0, wave 0)
-  if (blockIdx.x == 0 && wave == 0 && lane < head) {
+  // the elements before the first aligned one (wave 0)
+  if (wave == 0 && lane < head) {
     uint32_t se;
     uint64_t ve;
     split(J, lane, se, ve);
     patch_store<OP>(J, lane, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
   }
-  if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane == 0) raise_flag(flags, ZG_FLAG_BUDGET);
+}
+
+template <int OP, int KIND>
+__global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict__ T,
+                                              uint32_t dmax, uint32_t *flags, uint32_t tile,
+                                              uint32_t head, uint32_t qcap) {
+  __shared__ BlockLds L;
+  load_tabs<OP>(T, L.t);
+  const double r = T->r;
+  const LaneConst LC = lane_constants<OP, KIND>(T);
+  bool budget = false;
+  const uint64_t bt = (uint64_t)tile * (blockDim.x >> 6);
+  const uint64_t b0 = uni64((uint64_t)blockIdx.x * bt + head);
+  const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
+  zig_block<OP, KIND>(J, L, T, LC, r, dmax, tile, b0, b1, blockIdx.x == 0 ? head : 0u, qcap,
+                      budget);
+  if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane_id() == 0)
+    raise_flag(flags, ZG_FLAG_BUDGET);
 }
 
 // ---------------------------------------------------------------- kernels
 
-// One tile per wave.  Tile t covers [head + t*tile, head + (t+1)*tile).
-template <int OP, int KIND>
-__global__ __launch_bounds__(1024) void k_fill(Job J, const DevTables *__restrict__ T,
-                                               uint32_t dmax, uint32_t *flags, uint32_t tile,
-                                               uint32_t head) {
-  __shared__ Fast64 s_f64[ZG_LAYERS];
-  __shared__ Fast32 s_f32[ZG_LAYERS];
-  extern __shared__ uint32_t s_q[];   // waves x (QCAP + TCAP)
-  load_fast(T, s_f64, s_f32, OP != OP_ZIG32, OP == OP_ZIG32);
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+// Polar method: one tile per wave; tile t covers [head + t tile, + tile).
+template <int KIND>
+__global__ __launch_bounds__(1024) void k_polar(Job J, const DevTables *__restrict__ T,
+                                                uint32_t dmax, uint32_t *flags, uint32_t tile,
+                                                uint32_t head) {
+  extern __shared__ uint32_t s_q[];   // waves x QCAP
+  const uint32_t wave = uni(threadIdx.x >> 6);
   const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   const uint64_t b = head + gw * tile;
-  Ctx C{T, s_f64, s_f32, dmax, flags};
+  const PolarCtx C{T, dmax, flags};
   if (b < J.n_total || (gw == 0 && head)) {
-    LaneConst LC = lane_constants<OP, KIND>(T);
-    uint64_t e_end = b + tile < J.n_total ? b + tile : J.n_total;
-    uint64_t e_begin = b < e_end ? b : e_end;
-    process_tile<OP, KIND>(J, C, LC, s_q + wave * (QCAP + TCAP), e_begin, e_end, head, gw == 0);
+    const LaneConst LC = lane_constants<OP_POLAR, KIND>(T);
+    const uint64_t e_end = b + tile < J.n_total ? b + tile : J.n_total;
+    const uint64_t e_begin = b < e_end ? b : e_end;
+    polar_tile<KIND>(J, C, LC, s_q + wave * QCAP, e_begin, e_end, head, gw == 0);
   }
 }
 
@@ -1404,72 +949,85 @@ __global__ __launch_bounds__(1024) void k_reserve(DevRequest *R, const BatchHead
   }
 }
 
-// Persistent batch kernel: waves take tiles t = gw, gw + W, ... of the
-// concatenated tile space; each tile belongs to one request (found by binary
-// search over tile0), so the branch on its op is uniform.  The wave that
-// finishes a request's last tile writes its completion word.
-__global__ __launch_bounds__(512) void k_batch(DevRequest *R, const BatchHeader *H,
-                                                const DevTables *__restrict__ T,
-                                                uint32_t *flags) {
-  __shared__ Fast64 s_f64[ZG_LAYERS];
-  __shared__ Fast32 s_f32[ZG_LAYERS];
-  extern __shared__ uint32_t s_q[];   // waves x (QCAP + TCAP)
-  load_fast(T, s_f64, s_f32, true, true);
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-  const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
-  const uint32_t nreq = H->nreq;
-  const uint64_t total = H->total_tiles;
+// Publishes the completion word of every request of a batch.  It runs after
+// the class kernels (a graph dependency), so all their stores are released
+// by the kernel boundary; the first indices were written by the reserve
+// kernel before them.
+__global__ __launch_bounds__(256) void k_complete(const DevRequest *R, const BatchHeader *H) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= H->nreq) return;
+  const DevRequest &rq = R[i];
+  if (!rq.done_flag) return;
+  __threadfence_system();
+  const uint32_t val = rq.done_value | (rq.status ? 0x80000000u : 0u);
+  __hip_atomic_store(rq.done_flag, val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Batch work of one ziggurat class: a persistent grid takes the class's items
+// (workgroup tiles of its requests) in turn and runs each as the plain fill
+// runs one workgroup tile.
+template <int OP, int KIND>
+__global__ __launch_bounds__(1024) void k_bzig(DevRequest *R, const BatchHeader *H,
+                                               const DevTables *__restrict__ T,
+                                               uint32_t *flags) {
+  constexpr int C = batch_class(OP, KIND);
+  const uint32_t cnt = H->cls_cnt[C];
+  if (blockIdx.x >= cnt) return;
+  __shared__ BlockLds L;
+  load_tabs<OP>(T, L.t);
+  const uint64_t *items = (const uint64_t *)((const char *)H + H->items_off);
+  const uint32_t off = H->cls_off[C];
   const uint32_t dmax = H->dmax;
-  Ctx C{T, s_f64, s_f32, dmax, flags};
-  for (uint64_t t = gw; t < total; t += nw) {
-    // the request with tile0 <= t < tile0 + tiles (every request has >= 1 tile)
-    uint32_t lo = 0, hi = nreq;
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (R[mid].tile0 <= t)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    const uint32_t ri = __builtin_amdgcn_readfirstlane(lo);
-    DevRequest &rq = R[ri];
-    const Job J = rq.job;
-    const uint64_t lt = t - rq.tile0;
+  const uint32_t nw = blockDim.x >> 6;
+  const double r = T->r;
+  const LaneConst LC = lane_constants<OP, KIND>(T);
+  bool budget = false;
+  for (uint32_t k = blockIdx.x; k < cnt; k += gridDim.x) {
+    const uint64_t it = items[off + k];
+    const DevRequest &rq = R[(uint32_t)(it >> 32)];
+    const uint32_t j = (uint32_t)it;
     if (rq.status == 0) {
-      const uint64_t b = rq.head + lt * rq.tile;
-      uint64_t e_end = b + rq.tile < J.n_total ? b + rq.tile : J.n_total;
-      uint64_t e_begin = b < e_end ? b : e_end;
-#define ZG_TILE_CASE(OPV)                                                                  \
-  case OPV: {                                                                              \
-    if (J.kind == ZG_JAVA_LCG48) {                                                         \
-      LaneConst LC = lane_constants<OPV, ZG_JAVA_LCG48>(T);                                \
-      process_tile<OPV, ZG_JAVA_LCG48>(J, C, LC, s_q + wave * (QCAP + TCAP), e_begin, e_end, rq.head, \
-                                       lt == 0);                                           \
-    } else {                                                                               \
-      LaneConst LC = lane_constants<OPV, ZG_SPLITMIX64>(T);                                \
-      process_tile<OPV, ZG_SPLITMIX64>(J, C, LC, s_q + wave * (QCAP + TCAP), e_begin, e_end, rq.head, \
-                                       lt == 0);                                           \
-    }                                                                                      \
-  } break;
-      switch (J.op) {
-        ZG_TILE_CASE(OP_ZIG64)
-        ZG_TILE_CASE(OP_ZIG32)
-        ZG_TILE_CASE(OP_POLAR)
-        ZG_TILE_CASE(OP_MUTATE)
-        default: break;
-      }
-#undef ZG_TILE_CASE
+      const Job J = rq.job;
+      const uint64_t bt = (uint64_t)rq.tile * nw;
+      const uint64_t b0 = uni64(rq.head + j * bt);
+      const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
+      zig_block<OP, KIND>(J, L, T, LC, r, dmax, rq.tile, b0, b1, j == 0 ? rq.head : 0u, BQ,
+                          budget);
     }
-    // completion: make this wave's stores visible, count the tile down
-    __threadfence();
-    if (lane_id() == 0) {
-      uint32_t before = atomicSub(&rq.remaining, 1u);
-      if (before == 1 && rq.done_flag) {
-        __threadfence_system();
-        uint32_t val = rq.done_value | (rq.status ? 0x80000000u : 0u);
-        __hip_atomic_store(rq.done_flag, val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
+    __syncthreads();   // the next tile resets the queue
+  }
+  if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane_id() == 0)
+    raise_flag(flags, ZG_FLAG_BUDGET);
+}
+
+// Batch work of the polar class: every wave of a workgroup tile runs the
+// per-wave polar path over its part.
+template <int KIND>
+__global__ __launch_bounds__(1024) void k_bpolar(DevRequest *R, const BatchHeader *H,
+                                                 const DevTables *__restrict__ T,
+                                                 uint32_t *flags) {
+  constexpr int C = batch_class(OP_POLAR, KIND);
+  const uint32_t cnt = H->cls_cnt[C];
+  if (blockIdx.x >= cnt) return;
+  extern __shared__ uint32_t s_q[];   // waves x QCAP
+  const uint64_t *items = (const uint64_t *)((const char *)H + H->items_off);
+  const uint32_t off = H->cls_off[C];
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const PolarCtx Cx{T, H->dmax, flags};
+  const LaneConst LC = lane_constants<OP_POLAR, KIND>(T);
+  for (uint32_t k = blockIdx.x; k < cnt; k += gridDim.x) {
+    const uint64_t it = items[off + k];
+    const DevRequest &rq = R[(uint32_t)(it >> 32)];
+    const uint32_t j = (uint32_t)it;
+    if (rq.status == 0) {
+      const Job J = rq.job;
+      const uint64_t b = rq.head + ((uint64_t)j * nw + wave) * rq.tile;
+      const uint64_t e_end = b + rq.tile < J.n_total ? b + rq.tile : J.n_total;
+      const uint64_t e_begin = b < e_end ? b : e_end;
+      const bool with_head = j == 0 && wave == 0;
+      if (e_begin < e_end || (with_head && rq.head))
+        polar_tile<KIND>(J, Cx, LC, s_q + wave * QCAP, e_begin, e_end, rq.head, with_head);
     }
   }
 }
@@ -1495,9 +1053,9 @@ static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax
     uint64_t tiles = (body + tile - 1) / tile;
     if (tiles == 0) tiles = 1;   // head-only jobs still need wave 0
     uint64_t blocks = (tiles + waves - 1) / waves;
-    hipLaunchKernelGGL((k_fill<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * waves),
-                       (size_t)waves * (QCAP + TCAP) * sizeof(uint32_t), stream, J, T, dmax, flags,
-                       tile, head);
+    hipLaunchKernelGGL((k_polar<KIND>), dim3((uint32_t)blocks), dim3(64 * waves),
+                       (size_t)waves * QCAP * sizeof(uint32_t), stream, J, T, dmax, flags, tile,
+                       head);
   }
   return hipGetLastError();
 }
@@ -1540,7 +1098,23 @@ hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, 
 }
 
 const void *kernel_reserve() { return (const void *)k_reserve; }
-const void *kernel_batch() { return (const void *)k_batch; }
-size_t batch_lds_bytes(uint32_t waves) { return (size_t)waves * (QCAP + TCAP) * sizeof(uint32_t); }
+const void *kernel_complete() { return (const void *)k_complete; }
+
+const void *kernel_batch_class(int cls) {
+  switch (cls) {
+    case batch_class(OP_ZIG64, ZG_SPLITMIX64): return (const void *)k_bzig<OP_ZIG64, ZG_SPLITMIX64>;
+    case batch_class(OP_ZIG64, ZG_JAVA_LCG48): return (const void *)k_bzig<OP_ZIG64, ZG_JAVA_LCG48>;
+    case batch_class(OP_ZIG32, ZG_SPLITMIX64): return (const void *)k_bzig<OP_ZIG32, ZG_SPLITMIX64>;
+    case batch_class(OP_ZIG32, ZG_JAVA_LCG48): return (const void *)k_bzig<OP_ZIG32, ZG_JAVA_LCG48>;
+    case batch_class(OP_MUTATE, ZG_SPLITMIX64): return (const void *)k_bzig<OP_MUTATE, ZG_SPLITMIX64>;
+    case batch_class(OP_MUTATE, ZG_JAVA_LCG48): return (const void *)k_bzig<OP_MUTATE, ZG_JAVA_LCG48>;
+    case batch_class(OP_POLAR, ZG_SPLITMIX64): return (const void *)k_bpolar<ZG_SPLITMIX64>;
+    default: return (const void *)k_bpolar<ZG_JAVA_LCG48>;
+  }
+}
+
+size_t batch_class_lds_bytes(int cls, uint32_t waves) {
+  return cls >= batch_class(OP_POLAR, ZG_SPLITMIX64) ? (size_t)waves * QCAP * sizeof(uint32_t) : 0;
+}
 
 }  // namespace zg

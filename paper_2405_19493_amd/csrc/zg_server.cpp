@@ -15,11 +15,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -118,7 +120,12 @@ struct zg_server {
   std::condition_variable cv_poll;   // completion thread: new requests in flight
   std::deque<uint64_t> pending;
   std::unordered_map<uint64_t, Ticket> tickets;
-  std::vector<uint64_t> inflight;
+  // ticket that owns each completion record (0: free); read by the
+  // completion thread without the lock
+  std::unique_ptr<std::atomic<uint64_t>[]> owner;
+  uint64_t n_inflight = 0;
+  std::vector<uint32_t> active;       // records in use, in any order
+  std::vector<uint32_t> active_pos;   // position of each record in `active`
   uint64_t next_ticket = 1;
   bool stop = false;
 
@@ -144,10 +151,16 @@ void zg_server::finish(uint64_t id, Ticket &t, int32_t status, uint64_t first) {
   t.c.complete_s = now();
   t.c.done = 1;
   if (t.rec >= 0) {
+    owner[t.rec].store(0, std::memory_order_relaxed);
+    const uint32_t pos = active_pos[t.rec];
+    active[pos] = active.back();
+    active_pos[active[pos]] = pos;
+    active.pop_back();
     free_recs.push_back(t.rec);
     t.rec = -1;
+    --n_inflight;
   }
-  inflight.erase(std::remove(inflight.begin(), inflight.end(), id), inflight.end());
+  (void)id;
   ++completed;
   if (status == ZG_OK) variates += t.req.n;
   latencies.push_back(t.c.complete_s - t.c.arrival_s);
@@ -190,13 +203,16 @@ void zg_server::batch_loop() {
       free_recs.pop_back();
       recs[t.rec].done = 0;
       recs[t.rec].first = 0;
+      owner[t.rec].store(id, std::memory_order_release);
+      active_pos[t.rec] = (uint32_t)active.size();
+      active.push_back((uint32_t)t.rec);
+      ++n_inflight;
       t.c.d_out = arena_base + off;
       t.c.admit_s = now();
       inflight_bytes += t.bytes;
       peak_inflight_bytes = std::max(peak_inflight_bytes, inflight_bytes);
       pending.pop_front();
       batch.push_back(id);
-      inflight.push_back(id);
     }
     if (batch.empty()) {
       // full: wait for a completion or a release
@@ -239,33 +255,42 @@ void zg_server::batch_loop() {
 }
 
 void zg_server::complete_loop() {
-  std::vector<std::pair<uint64_t, int32_t>> watch;
-  std::unique_lock<std::mutex> lk(mu);
+  std::vector<uint32_t> watch;
+  std::vector<std::pair<uint64_t, uint32_t>> hits;   // (ticket, record)
+  uint32_t idle = 0;
   for (;;) {
-    cv_poll.wait_for(lk, std::chrono::microseconds(200),
-                     [&] { return !inflight.empty() || (stop && pending.empty()); });
-    if (inflight.empty()) {
-      if (stop && pending.empty()) break;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (n_inflight == 0) {
+        if (stop && pending.empty()) break;
+        cv_poll.wait_for(lk, std::chrono::microseconds(200));
+        continue;
+      }
+      watch.assign(active.begin(), active.end());
+    }
+    // read the records without the lock; the device writes them
+    hits.clear();
+    for (uint32_t k : watch) {
+      const uint64_t id = owner[k].load(std::memory_order_acquire);
+      if (id && __atomic_load_n(&recs[k].done, __ATOMIC_ACQUIRE)) hits.emplace_back(id, k);
+    }
+    if (hits.empty()) {
+      // yield for a while after the last completion, then back off to short sleeps
+      if (++idle < 2000)
+        std::this_thread::yield();
+      else
+        std::this_thread::sleep_for(std::chrono::microseconds(10));
       continue;
     }
-    watch.clear();
-    for (uint64_t id : inflight) watch.emplace_back(id, tickets[id].rec);
-    lk.unlock();
-    // poll the records without the lock; they are written by the device
-    std::vector<std::pair<size_t, uint32_t>> hits;
-    for (size_t k = 0; k < watch.size(); ++k) {
-      const uint32_t v = __atomic_load_n(&recs[watch[k].second].done, __ATOMIC_ACQUIRE);
-      if (v) hits.emplace_back(k, v);
-    }
-    if (hits.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
-    lk.lock();
+    idle = 0;
+    std::lock_guard<std::mutex> lk(mu);
     for (auto &h : hits) {
-      const uint64_t id = watch[h.first].first;
-      auto it = tickets.find(id);
+      if (owner[h.second].load(std::memory_order_relaxed) != h.first) continue;
+      auto it = tickets.find(h.first);
       if (it == tickets.end() || it->second.c.done) continue;
-      const HostRec &rec = recs[watch[h.first].second];
-      const uint64_t first = __atomic_load_n(&rec.first, __ATOMIC_ACQUIRE);
-      finish(id, it->second, (h.second & 0x80000000u) ? ZG_ERANGE : ZG_OK, first);
+      const uint32_t v = __atomic_load_n(&recs[h.second].done, __ATOMIC_ACQUIRE);
+      const uint64_t first = __atomic_load_n(&recs[h.second].first, __ATOMIC_ACQUIRE);
+      finish(h.first, it->second, (v & 0x80000000u) ? ZG_ERANGE : ZG_OK, first);
     }
   }
 }
@@ -303,6 +328,10 @@ zg_status zg_server_create(zg_ctx *ctx, const zg_server_config *cfg, zg_server *
     return st == ZG_OK ? ZG_EHIP : st;
   }
   std::memset(s->recs, 0, sizeof(HostRec) * cfg->max_inflight);
+  s->owner.reset(new std::atomic<uint64_t>[cfg->max_inflight]);
+  for (uint32_t k = 0; k < cfg->max_inflight; ++k) s->owner[k].store(0);
+  s->active_pos.assign(cfg->max_inflight, 0);
+  s->active.reserve(cfg->max_inflight);
   s->arena.init(s->cfg.mem_cap_bytes);
   for (int32_t k = (int32_t)cfg->max_inflight - 1; k >= 0; --k) s->free_recs.push_back(k);
   s->batcher = std::thread([s] { s->batch_loop(); });
@@ -383,7 +412,7 @@ zg_status zg_server_release(zg_server *s, uint64_t ticket) {
 zg_status zg_server_drain(zg_server *s) {
   if (!s) return ZG_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
-  s->cv_done.wait(lk, [&] { return s->pending.empty() && s->inflight.empty(); });
+  s->cv_done.wait(lk, [&] { return s->pending.empty() && s->n_inflight == 0; });
   return ZG_OK;
 }
 
@@ -408,6 +437,53 @@ zg_status zg_server_stats_get(zg_server *s, zg_server_stats *out) {
 }
 
 double zg_server_now(const zg_server *s) { return s ? s->now() : 0.0; }
+
+zg_status zg_server_replay(zg_server *s, const zg_server_request *reqs, uint32_t n,
+                           uint64_t *first_out, double timeout_s) {
+  if (!s || (n && !reqs)) return ZG_EINVAL;
+  std::vector<uint64_t> tickets(n, 0);
+  std::vector<char> ready(n, 0);
+  std::mutex rmu;
+  std::condition_variable rcv;
+  zg_status result = ZG_OK;
+  const double base = s->now();
+  const double deadline = base + timeout_s;
+  // releases completed requests in submission order
+  std::thread releaser([&] {
+    for (uint32_t k = 0; k < n; ++k) {
+      {
+        std::unique_lock<std::mutex> lk(rmu);
+        rcv.wait(lk, [&] { return ready[k] != 0; });
+        if (ready[k] < 0) continue;
+      }
+      zg_completion c{};
+      const double left = deadline - s->now();
+      zg_status st = left > 0 ? zg_server_wait(s, tickets[k], left, &c) : ZG_EBUSY;
+      if (st != ZG_OK) {
+        result = st;
+        continue;
+      }
+      if (first_out) first_out[k] = c.first_index;
+      if (c.status != ZG_OK && result == ZG_OK) result = c.status;
+      zg_server_release(s, tickets[k]);
+    }
+  });
+  for (uint32_t k = 0; k < n; ++k) {
+    zg_server_request r = reqs[k];
+    r.arrival_s = base + reqs[k].arrival_s;
+    while (s->now() < r.arrival_s) {
+    }
+    zg_status st = zg_server_submit(s, &r, &tickets[k]);
+    {
+      std::lock_guard<std::mutex> lk(rmu);
+      ready[k] = st == ZG_OK ? 1 : -1;
+      if (st != ZG_OK && result == ZG_OK) result = st;
+    }
+    rcv.notify_one();
+  }
+  releaser.join();
+  return result;
+}
 
 zg_status zg_server_destroy(zg_server *s) {
   if (!s) return ZG_OK;

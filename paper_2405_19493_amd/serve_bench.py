@@ -110,28 +110,64 @@ def alone_vs_mix(ctx, keep, trace, seed_of_handle, stream_of_handle):
     return bad
 
 
-def run(ctx, duration_s=5.0, rate=20000.0, n_handles=65536, mem_cap=64 << 30, window_us=200,
-        sample_every=97, sample_n_max=1 << 20, modes=("batched", "per_request")):
-    """Runs the trace in each mode; returns a dict for the bench line."""
+def replay_mode(ctx, mode, trace, handles, mem_cap, window_us):
+    """C-driven open-loop replay of the trace; returns the server's figures."""
+    t_arr, sizes, dtypes, hidx = trace
+    srv = Z.Server(ctx, mem_cap_bytes=mem_cap, max_inflight=8192, max_batch=4096,
+                   batch_window_us=window_us, n_streams=2, mode=mode)
+    hs = np.asarray(handles, dtype=np.int64)[hidx]
+    t0 = time.perf_counter()
+    srv.replay(hs, sizes, dtypes, t_arr, timeout_s=600.0)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    span = st["last_complete_s"] - st["first_arrival_s"]
+    return {"requests": int(st["completed"]), "batches": int(st["batches"]),
+            "variates_per_s": st["variates"] / span if span > 0 else 0.0,
+            "p50_latency_ms": st["p50_latency_s"] * 1e3, "p99_latency_ms": st["p99_latency_s"] * 1e3,
+            "max_latency_ms": st["max_latency_s"] * 1e3,
+            "peak_inflight_bytes": int(st["peak_inflight_bytes"]), "wall_s": wall}
+
+
+def run(ctx, duration_s=5.0, rate=20000.0, n_handles=65536, mem_cap=64 << 30, window_us=0,
+        check_s=1.0, sweep=(20000, 50000, 100000, 200000, 400000), sweep_s=1.0,
+        sample_every=97, sample_n_max=1 << 20):
+    """The serving figures for the bench line: the trace at `rate` replayed
+    in both modes (headline p50/p99 and variates/s), an alone-vs-mix bit check
+    on sampled requests, and a rate sweep to saturation."""
     free, _total = torch.cuda.mem_get_info()
     mem_cap = int(min(mem_cap, free * 0.6)) & ~255
-    trace = make_trace(rate, duration_s, n_handles)
-    sample = set(range(0, len(trace[0]), sample_every))
-    out = {"offered_rate_per_s": rate, "duration_s": duration_s, "requests": len(trace[0]),
-           "mean_request_variates": float(trace[1].mean()) if len(trace[0]) else 0.0,
-           "arena_bytes": mem_cap}
-    for name in modes:
-        seed_base = 1000 if name == "batched" else 5000
-        handles = [ctx.zg_stream_open(seed_base + h, h, Z.ZG_SPLITMIX64) for h in range(n_handles)]
-        mode = Z.ZG_SERVE_BATCHED if name == "batched" else Z.ZG_SERVE_PER_REQUEST
-        res, keep, errors = run_mode(ctx, mode, trace, handles, mem_cap, sample, sample_n_max,
-                                     seed_base, window_us)
-        res["alone_vs_mix_checked"] = len(keep)
-        res["alone_vs_mix_mismatch"] = alone_vs_mix(ctx, keep, trace, lambda h: seed_base + h,
-                                                    lambda h: h)
-        if errors:
-            res["first_errors"] = [str(e) for e in errors[:3]]
+    out = {"offered_rate_per_s": rate, "duration_s": duration_s, "arena_bytes": mem_cap,
+           "batch_window_us": window_us}
+    modes = (("batched", Z.ZG_SERVE_BATCHED), ("per_request", Z.ZG_SERVE_PER_REQUEST))
+    handles = [ctx.zg_stream_open(1000 + h, h, Z.ZG_SPLITMIX64) for h in range(n_handles)]
+    try:
+        trace = make_trace(rate, duration_s, n_handles)
+        out["requests"] = len(trace[0])
+        out["mean_request_variates"] = float(trace[1].mean()) if len(trace[0]) else 0.0
+        for name, mode in modes:
+            out[name] = replay_mode(ctx, mode, trace, handles, mem_cap, window_us)
+        # alone-vs-mix: a shorter trace driven from Python so outputs can be kept
+        ctrace = make_trace(rate, check_s, n_handles, seed=6)
+        sample = set(range(0, len(ctrace[0]), sample_every))
+        for name, mode in modes:
+            _res, keep, errors = run_mode(ctx, mode, ctrace, handles, mem_cap, sample,
+                                          sample_n_max, 1000, window_us)
+            out[name]["alone_vs_mix_checked"] = len(keep)
+            out[name]["alone_vs_mix_mismatch"] = alone_vs_mix(ctx, keep, ctrace,
+                                                              lambda h: 1000 + h, lambda h: h)
+            out[name]["errors"] = len(errors)
+        rows = []
+        for r in sweep:
+            tr = make_trace(float(r), sweep_s, n_handles, seed=7)
+            row = {"rate_per_s": r}
+            for name, mode in modes:
+                res = replay_mode(ctx, mode, tr, handles, mem_cap, window_us)
+                row[name] = {k: res[k] for k in ("variates_per_s", "p50_latency_ms",
+                                                 "p99_latency_ms", "batches")}
+            rows.append(row)
+        out["sweep"] = rows
+    finally:
         for h in handles:
             ctx.zg_stream_close(h)
-        out[name] = res
     return out

@@ -52,7 +52,7 @@ def _uneven_requests(count, rng, max_log2=16, with_mutate=True):
     return reqs
 
 
-@pytest.mark.parametrize("count,seed", [(1, 1), (37, 2), (300, 3)])
+@pytest.mark.parametrize("count,seed", [(1, 1), (5, 4), (7, 5), (37, 2), (300, 3)])
 def test_batch_matches_oracle(ctx, zg, count, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
     reqs = _uneven_requests(count, rng)

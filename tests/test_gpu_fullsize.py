@@ -1,0 +1,95 @@
+"""Full-size GPU checks, in the launch configurations bench.py times:
+
+- sampled parity at 2^28 variates (c2 ziggurat and polar: 65536 streams x
+  4096, SplitMix64 seed 7; c3: one LCG48 stream, seed 123456789): 2^16 random
+  positions compared element by element with the oracle, under the rules of
+  tests/parity.py;
+- statistics of GPU output at 1e8: moments, Kolmogorov-Smirnov against Phi
+  and the tail frequency erfc(r/sqrt 2), the same pins the oracle passes.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import coracle as orc
+from oracle import stats
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+N_STREAMS, N_PER = 65536, 4096
+SAMPLES = 1 << 16
+Z_MAX = 5.0
+
+
+def _sample_positions(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.unique(rng.integers(0, n, SAMPLES))
+
+
+def _oracle_at(kind, seed, positions, n_per, method=0):
+    """Oracle values and classes of single elements (stream = e // n_per)."""
+    vals = np.empty(positions.size)
+    cls = np.empty(positions.size, dtype=np.uint8)
+    for k, e in enumerate(positions):
+        s, v = divmod(int(e), n_per)
+        if method == 1:
+            p = v & ~1   # polar works on pairs: evaluate the pair, take the element
+            x, c, _ = orc.fill_polar(kind, seed, s, p, 2, nthreads=1)
+            vals[k], cls[k] = x[v - p], c[v - p]
+        else:
+            x, c, _ = orc.fill_f64(kind, seed, s, v, 1, nthreads=1)
+            vals[k], cls[k] = x[0], c[0]
+    return vals, cls
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_c2_sampled_parity(ctx, zg, method):
+    n = N_STREAMS * N_PER
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.zg_fill_streams(out, N_PER, N_STREAMS, method=method, kind=zg.ZG_SPLITMIX64, seed=7)
+    pos = _sample_positions(n, 31 + method)
+    got = out[torch.from_numpy(pos).cuda()].cpu().numpy()
+    # the stream-boundary neighbourhood too: first and last element of some streams
+    edge = np.array([s * N_PER + o for s in (0, 1, 4095, 65535) for o in (0, 1, N_PER - 2, N_PER - 1)])
+    got_e = out[torch.from_numpy(edge).cuda()].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    want, cls = _oracle_at(orc.SM64, 7, pos, N_PER, method)
+    compare(got, want, cls, ("c2", method), polar=method == 1)
+    want_e, cls_e = _oracle_at(orc.SM64, 7, edge, N_PER, method)
+    compare(got_e, want_e, cls_e, ("c2 edges", method), polar=method == 1)
+    assert ctx.zg_error_flags() == 0
+
+
+def test_c3_lcg_sampled_parity(ctx, zg):
+    n = 1 << 28
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.zg_fill(out, kind=zg.ZG_JAVA_LCG48, seed=123456789, stream=0)
+    pos = _sample_positions(n, 33)
+    got = out[torch.from_numpy(pos).cuda()].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    want, cls = _oracle_at(orc.LCG48, 123456789, pos, n)
+    compare(got, want, cls, "c3")
+
+
+def _check_normal(x, r, label):
+    z = stats.moment_zscores(x)
+    assert all(abs(v) < Z_MAX for v in z.values()), (label, z)
+    D = stats.ks_statistic(x)
+    assert D < stats.ks_critical(x.size, 0.001), (label, D)
+    tz, k, e = stats.tail_count_z(x, r)
+    assert abs(tz) < Z_MAX, (label, k, e)
+
+
+@pytest.mark.parametrize("dtype,kind", [(torch.float64, 1), (torch.float32, 1), (torch.float64, 2)])
+def test_statistics_1e8(ctx, zg, dtype, kind):
+    n = 10 ** 8
+    out = torch.empty(n, dtype=dtype, device="cuda")
+    ctx.zg_fill(out, kind=kind, seed=42, stream=3, first_index=1000)
+    x = out.cpu().numpy().astype(np.float64)
+    del out
+    torch.cuda.empty_cache()
+    assert np.all(np.isfinite(x))
+    _check_normal(x, orc.table_dict()["r"], (str(dtype), kind))

@@ -129,3 +129,32 @@ def test_server_range_error_is_reported(ctx, zg):
     finally:
         srv.close()
         ctx.zg_stream_close(h)
+
+
+def test_server_replay_matches_counters(ctx, zg):
+    """The C-driven replay submits every request and releases its output;
+    counters advance by the sizes, in order."""
+    import numpy as np
+    h = [ctx.zg_stream_open(70 + k, k, zg.ZG_SPLITMIX64) for k in range(3)]
+    srv = zg.Server(ctx, mem_cap_bytes=8 << 20, max_inflight=32, max_batch=16, batch_window_us=0,
+                    n_streams=2, mode=0)
+    try:
+        rng = np.random.Generator(np.random.PCG64(3))
+        m = 300
+        sizes = rng.integers(1, 5000, m)
+        hid = rng.integers(0, 3, m)
+        arrivals = np.cumsum(rng.exponential(1e-5, m))
+        first = srv.replay(np.array(h)[hid], sizes, np.zeros(m, dtype=np.int64), arrivals,
+                           timeout_s=60.0, want_first=True)
+        running = [0, 0, 0]
+        for k in range(m):
+            assert first[k] == running[hid[k]], k
+            running[hid[k]] += int(sizes[k])
+        st = srv.stats()
+        assert st["completed"] == m and st["inflight_bytes"] == 0
+        for k in range(3):
+            assert ctx.zg_stream_get_counter(h[k]) == running[k]
+    finally:
+        srv.close()
+        for x in h:
+            ctx.zg_stream_close(x)
