@@ -37,6 +37,8 @@ def parse():
                    help="restrict the timed kernels (for profiling runs)")
     p.add_argument("--serve-seconds", type=float, default=5.0,
                    help="serving-loop run per mode (open-loop Poisson, 20k requests/s); 0 = skip")
+    p.add_argument("--autotune", action="store_true",
+                   help="run the launch-shape autotuner (zg_autotune) before timing")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the LCG, batch and mutation rows (profiling runs)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -223,6 +225,9 @@ def main():
 
     n = N_STREAMS * N_PER
     ctx = Z.Context(0)
+    if args.autotune:
+        ctx.zg_autotune(None, 1 << 30, use_cache=False)
+    tune = ctx.zg_get_tune(Z.ZG_TUNE_FILL_F64)
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     out.zero_()
 
@@ -268,6 +273,9 @@ def main():
                                "65536 streams x 4096, contiguous float64 (2 GiB); "
                                "polar fill of the same shape timed beside it",
                    "method": "ziggurat" if main_key == "zig" else "polar",
+                   "launch": {"tile": tune[0], "waves_per_block": tune[1],
+                              "persistent_blocks_per_cu": tune[2],
+                              "autotuned": bool(args.autotune)},
                    "variates_per_step": n, "streams": N_STREAMS, "per_stream": N_PER},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -17,10 +17,10 @@ using namespace zg;
 namespace {
 
 const zg_tune DEFAULT_TUNE[ZG_TUNE_CLASSES] = {
-    {1024, 16, 2, 0},   // FILL_F64
-    {2048, 16, 2, 0},   // FILL_F32
-    {2048, 8, 2, 0},    // POLAR
-    {1024, 16, 2, 0},   // MUTATE
+    {2048, 16, 2, 0},   // FILL_F64: persistent, at most 2 workgroups per CU
+    {4096, 16, 2, 0},   // FILL_F32
+    {2048, 8, 0, 0},    // POLAR
+    {2048, 16, 2, 0},   // MUTATE
     {2048, 8, 4, 0},    // BATCH (k_batch is bounded to 512 threads)
 };
 
@@ -85,7 +85,7 @@ zg_status launch_job(zg_ctx *ctx, const Job &J, hipStream_t stream) {
   const zg_tune &t = ctx->tune[tune_class(J.op)];
   uint32_t head = head_of(J.out, J.op, J.n_total);
   hipError_t e = launch_fill(J, ctx->d_tables, ctx->dmax, ctx->d_flags, t.tile, t.waves_per_block,
-                             head, t.queue_cap, stream);
+                             head, t.queue_cap, t.batch_blocks_per_cu, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "launch_fill");
   return ZG_OK;
 }
@@ -419,7 +419,9 @@ zg_status zg_set_tune(zg_ctx *ctx, int cls, const zg_tune *in) {
   uint32_t ch = cls == ZG_TUNE_FILL_F32 ? 256u : 128u;
   if (in->tile == 0 || in->tile % ch || in->tile > (1u << 19)) return ZG_EINVAL;
   if (in->waves_per_block < 1 || in->waves_per_block > 16) return ZG_EINVAL;
-  if (in->batch_blocks_per_cu < 1 || in->batch_blocks_per_cu > 8) return ZG_EINVAL;
+  // plain fills: 0 = one workgroup per tile; the batch kernels need >= 1
+  if (in->batch_blocks_per_cu > 8 || (cls == ZG_TUNE_BATCH && in->batch_blocks_per_cu < 1))
+    return ZG_EINVAL;
   if (cls == ZG_TUNE_BATCH && in->tile % 256) return ZG_EINVAL;
   if (in->queue_cap > 2048) return ZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);

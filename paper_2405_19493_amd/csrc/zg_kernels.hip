@@ -844,20 +844,25 @@ DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
   }
 }
 
+// Plain fills: workgroup tile t covers [head + t bt, + bt), bt = waves x tile;
+// a workgroup takes tiles blockIdx.x, + gridDim.x, ... (one tile each when
+// the grid has one workgroup per tile).
 template <int OP, int KIND>
 __global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict__ T,
                                               uint32_t dmax, uint32_t *flags, uint32_t tile,
-                                              uint32_t head, uint32_t qcap) {
+                                              uint32_t head, uint32_t qcap, uint64_t ntiles) {
   __shared__ BlockLds L;
   load_tabs<OP>(T, L.t);
   const double r = T->r;
   const LaneConst LC = lane_constants<OP, KIND>(T);
   bool budget = false;
   const uint64_t bt = (uint64_t)tile * (blockDim.x >> 6);
-  const uint64_t b0 = uni64((uint64_t)blockIdx.x * bt + head);
-  const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
-  zig_block<OP, KIND>(J, L, T, LC, r, dmax, tile, b0, b1, blockIdx.x == 0 ? head : 0u, qcap,
-                      budget);
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t b0 = uni64(t * bt + head);
+    const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
+    zig_block<OP, KIND>(J, L, T, LC, r, dmax, tile, b0, b1, t == 0 ? head : 0u, qcap, budget);
+    __syncthreads();   // the next tile resets the queue
+  }
   if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane_id() == 0)
     raise_flag(flags, ZG_FLAG_BUDGET);
 }
@@ -1037,18 +1042,36 @@ __global__ __launch_bounds__(1024) void k_bpolar(DevRequest *R, const BatchHeade
 template <int OP, int KIND>
 static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
                                  uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
-                                 hipStream_t stream) {
+                                 uint32_t resident, hipStream_t stream) {
   uint64_t body = J.n_total > head ? J.n_total - head : 0;
   if constexpr (OP != OP_POLAR) {
-    // whole steps per wave
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // small jobs: shorter tiles, so that every CU gets at least two workgroup
+    // tiles; whole steps per wave
+    const uint64_t fit = body / ((uint64_t)waves * (uint64_t)cus * 2);
+    if (fit < tile) tile = (uint32_t)(fit < BSTEP ? BSTEP : fit);
     tile = (tile + BSTEP - 1) / BSTEP * BSTEP;
     const uint64_t bt = (uint64_t)tile * waves;
-    uint64_t blocks = (body + bt - 1) / bt;
-    if (blocks == 0) blocks = 1;   // head-only jobs still need block 0
+    uint64_t ntiles = (body + bt - 1) / bt;
+    if (ntiles == 0) ntiles = 1;   // head-only jobs still need block 0
+    uint64_t blocks = ntiles;
+    if (resident) {
+      // persistent: at most `resident` workgroups per CU, capped by occupancy
+      int occ = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_zig<OP, KIND>,
+                                                        (int)(64 * waves), 0) != hipSuccess ||
+          occ < 1)
+        occ = 1;
+      const uint64_t cap = (uint64_t)cus * (resident < (uint32_t)occ ? resident : (uint32_t)occ);
+      if (blocks > cap) blocks = cap;
+    }
     const uint32_t qc = qcap == 0 || qcap > BQ ? BQ : qcap;
     hipLaunchKernelGGL((k_zig<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * waves), 0, stream, J,
-                       T, dmax, flags, tile, head, qc);
+                       T, dmax, flags, tile, head, qc, ntiles);
   } else {
+    (void)resident;
     (void)qcap;
     uint64_t tiles = (body + tile - 1) / tile;
     if (tiles == 0) tiles = 1;   // head-only jobs still need wave 0
@@ -1063,20 +1086,26 @@ static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax
 template <int OP>
 static hipError_t launch_kind(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
                               uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
-                              hipStream_t stream) {
+                              uint32_t resident, hipStream_t stream) {
   if (J.kind == ZG_JAVA_LCG48)
-    return launch_fill_op<OP, ZG_JAVA_LCG48>(J, T, dmax, flags, tile, waves, head, qcap, stream);
-  return launch_fill_op<OP, ZG_SPLITMIX64>(J, T, dmax, flags, tile, waves, head, qcap, stream);
+    return launch_fill_op<OP, ZG_JAVA_LCG48>(J, T, dmax, flags, tile, waves, head, qcap, resident,
+                                             stream);
+  return launch_fill_op<OP, ZG_SPLITMIX64>(J, T, dmax, flags, tile, waves, head, qcap, resident,
+                                           stream);
 }
 
 hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
                        uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
-                       hipStream_t stream) {
+                       uint32_t resident, hipStream_t stream) {
   switch (J.op) {
-    case OP_ZIG64: return launch_kind<OP_ZIG64>(J, T, dmax, flags, tile, waves, head, qcap, stream);
-    case OP_ZIG32: return launch_kind<OP_ZIG32>(J, T, dmax, flags, tile, waves, head, qcap, stream);
-    case OP_POLAR: return launch_kind<OP_POLAR>(J, T, dmax, flags, tile, waves, head, qcap, stream);
-    default: return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, qcap, stream);
+    case OP_ZIG64:
+      return launch_kind<OP_ZIG64>(J, T, dmax, flags, tile, waves, head, qcap, resident, stream);
+    case OP_ZIG32:
+      return launch_kind<OP_ZIG32>(J, T, dmax, flags, tile, waves, head, qcap, resident, stream);
+    case OP_POLAR:
+      return launch_kind<OP_POLAR>(J, T, dmax, flags, tile, waves, head, qcap, resident, stream);
+    default:
+      return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, qcap, resident, stream);
   }
 }
 

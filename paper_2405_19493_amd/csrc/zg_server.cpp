@@ -34,6 +34,8 @@ using namespace zg;
 namespace {
 
 constexpr uint64_t ARENA_ALIGN = 256;
+// at most this many requests admitted together are launched one by one
+constexpr size_t SOLO_MAX = 4;
 
 // First-fit allocator over [0, size) with coalescing of free neighbours.
 class Arena {
@@ -219,6 +221,10 @@ void zg_server::batch_loop() {
       cv_work.wait(lk);
       continue;
     }
+    // A batch completes as a whole, so a short request batched with a long
+    // one would wait for it: with no backlog (a few admitted at once) every
+    // request is launched alone; batches form once requests queue up.
+    const size_t groups = batch.size() <= SOLO_MAX ? batch.size() : 1;
     reqs.assign(batch.size(), zg_request{});
     flags.assign(batch.size(), nullptr);
     firsts.assign(batch.size(), nullptr);
@@ -234,23 +240,31 @@ void zg_server::batch_loop() {
       flags[k] = &d_recs[t.rec].done;
       firsts[k] = &d_recs[t.rec].first;
     }
-    hipStream_t stream = streams[next_stream++ % streams.size()];
-    ++batches;
+    const size_t per = batch.size() / groups;
+    batches += groups;
     lk.unlock();
-    BatchPlan plan;
-    zg_status st = plan_batch(ctx, reqs.data(), (uint32_t)reqs.size(), flags.data(), 1u, &plan,
-                              firsts.data());
-    BatchSlot *slot = nullptr;
-    if (st == ZG_OK) st = acquire_slot(ctx, &slot);
-    if (st == ZG_OK) {
-      st = slot->launch(ctx, plan, stream, /*full=*/true, nullptr);
-      release_slot(ctx, slot);
+    std::vector<zg_status> sts(groups, ZG_OK);
+    for (size_t g2 = 0; g2 < groups; ++g2) {
+      const size_t k0 = g2 * per, k1 = g2 + 1 == groups ? batch.size() : k0 + per;
+      hipStream_t stream = streams[next_stream++ % streams.size()];
+      BatchPlan plan;
+      zg_status st = plan_batch(ctx, reqs.data() + k0, (uint32_t)(k1 - k0), flags.data() + k0, 1u,
+                                &plan, firsts.data() + k0);
+      BatchSlot *slot = nullptr;
+      if (st == ZG_OK) st = acquire_slot(ctx, &slot);
+      if (st == ZG_OK) {
+        st = slot->launch(ctx, plan, stream, /*full=*/true, nullptr);
+        release_slot(ctx, slot);
+      }
+      sts[g2] = st;
     }
     lk.lock();
-    if (st != ZG_OK)
-      for (uint64_t id : batch) finish(id, tickets[id], st, 0);
-    else
-      cv_poll.notify_one();
+    for (size_t g2 = 0; g2 < groups; ++g2) {
+      const size_t k0 = g2 * per, k1 = g2 + 1 == groups ? batch.size() : k0 + per;
+      if (sts[g2] != ZG_OK)
+        for (size_t k = k0; k < k1; ++k) finish(batch[k], tickets[batch[k]], sts[g2], 0);
+    }
+    cv_poll.notify_one();
   }
 }
 

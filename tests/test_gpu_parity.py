@@ -249,3 +249,30 @@ def test_queue_overflow_path(ctx, zg, qcap):
     finally:
         for c, t in saved.items():
             ctx.zg_set_tune(c, *t)
+
+
+@pytest.mark.parametrize("cls_t,tdt", [(0, torch.float64), (1, torch.float32), (3, torch.float64)])
+def test_launch_shape_never_changes_bits(ctx, zg, cls_t, tdt):
+    """One workgroup per tile or a persistent grid, small or large tiles,
+    4 to 16 waves: the same bits (every variate is keyed by its index)."""
+    n = 3 * 65536 + 4097
+    saved = ctx.zg_get_tune(cls_t)
+    rng = np.random.Generator(np.random.PCG64(12))
+    x0 = torch.from_numpy(rng.uniform(-1, 1, n)).cuda() if cls_t == 3 else None
+    try:
+        ref = None
+        for tile, waves, res in [(2048, 16, 2), (256, 4, 0), (512, 8, 1), (4096, 16, 0), (1024, 16, 4)]:
+            ctx.zg_set_tune(cls_t, tile, waves, res)
+            out = dev_empty(n, tdt, 1)
+            if cls_t == 3:
+                out.copy_(x0)
+                ctx.zg_mutate(out, 0.5, kind=1, seed=2, stream=7, first_index=33)
+            else:
+                ctx.zg_fill_streams(out, 777, n // 777, kind=1, seed=2, stream0=7, first_index=33)
+                out = out[: (n // 777) * 777]
+            got = host(out).tobytes()
+            if ref is None:
+                ref = got
+            assert got == ref, (tile, waves, res)
+    finally:
+        ctx.zg_set_tune(cls_t, *saved)
