@@ -37,8 +37,8 @@ def parse():
                    help="restrict the timed kernels (for profiling runs)")
     p.add_argument("--serve-seconds", type=float, default=5.0,
                    help="serving-loop run per mode (open-loop Poisson, 20k requests/s); 0 = skip")
-    p.add_argument("--autotune", action="store_true",
-                   help="run the launch-shape autotuner (zg_autotune) before timing")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="skip the launch-shape autotuner (zg_autotune) and time the defaults")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the LCG, batch and mutation rows (profiling runs)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -225,8 +225,12 @@ def main():
 
     n = N_STREAMS * N_PER
     ctx = Z.Context(0)
-    if args.autotune:
-        ctx.zg_autotune(None, 1 << 30, use_cache=False)
+    if not args.no_autotune:
+        # the launch shape that is fastest on this device, at this size; cached
+        # per device so that later runs (a profiler's) time the same shape
+        import tempfile
+        cache = os.path.join(tempfile.gettempdir(), "zg_autotune_2p28.json")
+        ctx.zg_autotune(cache, 8 * N_STREAMS * N_PER, use_cache=True)
     tune = ctx.zg_get_tune(Z.ZG_TUNE_FILL_F64)
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     out.zero_()
@@ -275,7 +279,7 @@ def main():
                    "method": "ziggurat" if main_key == "zig" else "polar",
                    "launch": {"tile": tune[0], "waves_per_block": tune[1],
                               "persistent_blocks_per_cu": tune[2],
-                              "autotuned": bool(args.autotune)},
+                              "autotuned": not args.no_autotune},
                    "variates_per_step": n, "streams": N_STREAMS, "per_stream": N_PER},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -219,10 +219,16 @@ struct Queue {
   uint32_t qn;    // wave-uniform count
 };
 
+// Queue length at which a polar tile drains (down to POLAR_DRAIN - 1
+// entries): one full round of 64, soon after the placeholders were stored.
+constexpr uint32_t POLAR_DRAIN = 64;
+
 // Polar drain: one attempt per round, rejected pairs requeued.
 template <int KIND>
 DEV void drain_polar(const Job &J, const PolarCtx &C, Queue &Q, uint32_t keep, uint64_t e_base) {
   const uint32_t lane = lane_id();
+  // a rejected pair's placeholder was stored by another lane: order it first
+  if (Q.qn > keep) __threadfence_block();
   while (Q.qn > keep) {
     const uint32_t m = Q.qn < 64 ? Q.qn : 64;
     const bool has = lane < m;
@@ -383,7 +389,7 @@ DEV void polar_tile(const Job &J, const PolarCtx &C, const LaneConst &LC, uint32
     const uint64_t vc = uni64(J.first + r);
     polar_step<KIND>(J, C, LC, Q, ec, e_end, s, vc, clean, o0);
     o0 += STEP;
-    if (Q.qn > (uint32_t)QCAP - STEP) drain_polar<KIND>(J, C, Q, 63, e_base);
+    if (Q.qn >= POLAR_DRAIN) drain_polar<KIND>(J, C, Q, POLAR_DRAIN - 1, e_base);
     r += STEP;
     if (multi)
       while (r >= J.n_per) {

@@ -101,14 +101,17 @@ extern "C" zg_status zg_autotune(zg_ctx *ctx, const char *cache_path, uint64_t b
   if (e == hipSuccess) e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   zg_status st = e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "autotune setup");
-  const uint32_t tiles64[] = {1024, 2048, 4096, 8192};
-  const uint32_t waves[] = {4, 8, 16};
+  const uint32_t tiles64[] = {1024, 2048, 4096};
+  const uint32_t waves[] = {8, 16};
+  const uint32_t resident[] = {0, 2};   // one workgroup per tile, or persistent
   for (int c = 0; c < ZG_TUNE_CLASSES - 1 && st == ZG_OK; ++c) {
     zg_tune best = ctx->tune[c];
     float best_ms = 1e30f;
     for (uint32_t tl : tiles64)
-      for (uint32_t w : waves) {
-        zg_tune cand = {c == ZG_TUNE_FILL_F32 ? 2 * tl : tl, w, ctx->tune[c].batch_blocks_per_cu, 0};
+      for (uint32_t w : waves)
+        for (uint32_t res : resident) {
+        if (c == ZG_TUNE_POLAR && res) continue;   // the polar kernel is never persistent
+        zg_tune cand = {c == ZG_TUNE_FILL_F32 ? 2 * tl : tl, w, res, 0};
         st = zg_set_tune(ctx, c, &cand);
         if (st != ZG_OK) break;
         auto run = [&]() {
@@ -129,7 +132,7 @@ extern "C" zg_status zg_autotune(zg_ctx *ctx, const char *cache_path, uint64_t b
           }
         };
         if (c == ZG_TUNE_MUTATE) (void)hipMemsetAsync(buf, 0, bytes, s);
-        float ms = time_ms(run, s, a, b, 3);
+        float ms = time_ms(run, s, a, b, 5);
         if (ms < best_ms) {
           best_ms = ms;
           best = cand;
