@@ -123,6 +123,24 @@ def c3_lcg(ctx, Z, torch, steps, warmup):
                          "frac": 8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
+def f32_row(ctx, Z, torch, steps, warmup):
+    """The c2 layout in FP32 output (2^28 variates, 1 GiB; 4 B per variate)."""
+    n = N_STREAMS * N_PER
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+
+    def go():
+        ctx.zg_fill_streams(out, N_PER, N_STREAMS, method=Z.ZG_ZIGGURAT, kind=Z.ZG_SPLITMIX64,
+                            seed=SEED, stream0=0, first_index=0)
+
+    ms, _, _ = time_kernel(go, steps, warmup, torch)
+    del out
+    gbs = 4.0 * n / (ms * 1e-3) / 1e9
+    return {"workload": "ziggurat fill, 2^28 FP32, SplitMix64 seed 7, 65536 streams x 4096",
+            "value": n / (ms * 1e-3), "unit": "variates/s", "kernel_ms": ms,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS}}
+
+
 def c4_batch(ctx, Z, torch, reps):
     """10^4 uneven requests (sizes clamp(2^(20u)), 70% FP64) plus one mutation
     of 4096 x 1024 genes: one persistent batch launch against the same
@@ -296,6 +314,7 @@ def main():
     del out
     torch.cuda.empty_cache()
     if not args.no_extra:
+        line["f32"] = f32_row(ctx, Z, torch, args.steps, args.warmup)
         line["c3_lcg"] = c3_lcg(ctx, Z, torch, args.steps, args.warmup)
         line["c4_batch"] = c4_batch(ctx, Z, torch, 3)
     if args.serve_seconds > 0:

@@ -226,12 +226,17 @@ typedef struct zg_request {
   uint32_t reserved;
 } zg_request;
 
-/* Runs nreq uneven requests in one persistent launch (a hipGraph of the
- * descriptor upload, the counter reservation and the batch kernel).  Same
- * bits as the per-request calls.  first_out (host, optional): receives each
- * request's first index once the work has completed (valid after the stream
- * is synchronised).  Errors as zg_fill for any request; nothing is launched
- * if any request is invalid. */
+/* Runs nreq uneven requests as one launch: the descriptors and the work
+ * items (one per workgroup tile, grouped by op x uniform kind) are uploaded
+ * in one copy, a reservation kernel resolves the counter-keyed first indices
+ * in submission order, one persistent kernel per work class with work runs
+ * the tiles, and a completion kernel publishes the completion words.  Large
+ * batches launch as a hipGraph; batches of a few requests launch the same
+ * kernels directly.  Same bits as the per-request calls.  first_out (host,
+ * optional): receives each request's first index once the work has completed
+ * (the call then synchronises the stream).  Errors as zg_fill for any
+ * request; nothing is launched if any request is invalid.  Async on
+ * hip_stream otherwise. */
 zg_status zg_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, uint64_t *first_out,
                    void *hip_stream);
 
