@@ -4,13 +4,12 @@
 // ziggurat of Marsaglia-Tsang and Leong, as in GSL):
 //   keyed uniform word -> decode (layer, sign, j) -> fast accept j < k[i]
 //   with x = j w[i] (one multiply and one compare per lane) -> coalesced
-//   128-bit stores.  Lanes that fail the fast test are compacted with wave
-//   ballots and lane prefix counts into one LDS queue per workgroup; the
-//   queue is drained 64 entries at a time, each lane running the wedge /
-//   tail / retry loop of one queued variate, so the rare slow path does not
-//   diverge the fast one.  Every variate is a pure function of its index, so
-//   the launch shape, the queue order and the batch layout never change the
-//   bits.
+//   128-bit stores.  Elements that fail the fast test (about 2.8% of them)
+//   are appended to one LDS queue per workgroup; the queue is drained 64
+//   entries at a time, each lane running the wedge / tail / retry loop of
+//   one queued variate, so the rare slow path does not diverge the fast one.
+//   Every variate is a pure function of its index, so the launch shape, the
+//   queue order and the batch layout never change the bits.
 //
 // Also here: the polar method (Section 1; Java's nextGaussian), the uniform
 // word export, the per-word decision probe, and the batch kernels (counter
@@ -71,14 +70,15 @@ DEV uint64_t lcg_word_from(uint64_t S1) {
   return (((S1 >> 22) << 27) + (S2 >> 21)) << 11;
 }
 
-// Exact conversion of an integer below 2^53: hi * 2^32 + lo is representable,
-// so the fused multiply-add rounds nothing.
-// (The empty asm keeps the high half an opaque 32-bit value; otherwise the
-// compiler widens the conversion back to 64 bits and adds a zero.)
-DEV double to_f64(uint64_t j) {
-  uint32_t hi = (uint32_t)(j >> 32);
-  asm volatile("" : "+v"(hi));
-  return fma((double)hi, 4294967296.0, (double)(uint32_t)j);
+// The 53-bit integer j = bits 3..55 of a word (whi:wlo), as its two halves
+// (bit-field extracts, so that the conversion below stays two 32-bit ones).
+DEV uint32_t j_hi(uint32_t whi) { return __builtin_amdgcn_ubfe(whi, 3, 21); }
+DEV uint32_t j_lo(uint32_t whi, uint32_t wlo) { return __builtin_amdgcn_alignbit(whi, wlo, 3); }
+
+// Exact conversion of an integer below 2^53 given as hi * 2^32 + lo: the sum
+// is representable, so the fused multiply-add rounds nothing.
+DEV double to_f64(uint32_t hi, uint32_t lo) {
+  return fma((double)hi, 4294967296.0, (double)lo);
 }
 
 DEV double u53(uint64_t W) { return (double)(W >> 11) * 0x1p-53; }
@@ -196,7 +196,6 @@ DEV void raise_flag(uint32_t *flags, uint32_t bit) { atomicOr(flags, bit); }
 // The empty asm keeps the compiler from re-deriving that bit from the last
 // multiply of the hash (it would spend three extra multiplies on it).
 DEV double flip_hi(double x, uint32_t whi) {
-  asm volatile("" : "+v"(whi));
   return __hiloint2double(__double2hiint(x) ^ (int)((whi << 7) & 0x80000000u), __double2loint(x));
 }
 
@@ -313,11 +312,11 @@ DEV LaneConst lane_constants(const DevTables *T) {
 // FP64 fast path of one element: returns the signed candidate and whether the
 // integer test accepted it.
 DEV double fast64(const Fast64 *tab, uint64_t W, bool &fast) {
-  const uint32_t hi = (uint32_t)(W >> 32);
-  const Fast64 f = tab[hi >> 25];
-  const uint64_t j = (W >> 3) & MASK53;
-  fast = j < f.k;
-  return flip_hi(to_f64(j) * f.w, hi);
+  const uint32_t whi = (uint32_t)(W >> 32), wlo = (uint32_t)W;
+  const Fast64 f = tab[whi >> 25];
+  const uint32_t jh = j_hi(whi), jl = j_lo(whi, wlo);
+  fast = (((uint64_t)jh << 32) | jl) < f.k;
+  return flip_hi(to_f64(jh, jl) * f.w, whi);
 }
 
 // One polar step: a pair per lane (2 elements).
@@ -402,27 +401,25 @@ DEV void polar_tile(const Job &J, const PolarCtx &C, const LaneConst &LC, uint32
 
 // ------------------------------------------------ block-pooled ziggurat fill
 //
-// The plain ziggurat fills (FP64, FP32, mutation).  Every wave streams its
-// tile: 256 elements per step, all stored at once with 128-bit stores (an
+// The plain ziggurat fills (FP64, FP32, mutation).  The waves of a workgroup
+// stream its tile in groups of 4 steps of 256 elements, taken in turn from a
+// shared counter; each step is stored at once with 128-bit stores (an
 // element that failed the fast test gets a placeholder: the rejected
 // candidate, or for mutation the old value).  The slow elements of all waves
-// of the block go into one LDS queue (offsets from the block base).  After one
-// block barrier, which also orders every placeholder store before any patch,
-// the waves drain the pooled queue 64 entries at a time, each lane running the
+// go into one LDS queue (offsets from the tile base).  After one workgroup
+// barrier, which also orders every placeholder store before any patch, the
+// waves drain the pooled queue 64 entries at a time, each lane running the
 // whole attempt loop of one variate and storing its value.  Pooling keeps the
-// drain rounds nearly full: a block tile of 8 x 2048 elements has about 200
-// slow elements, while one wave's tile has about 25.
+// drain rounds nearly full: a tile of 16 x 2048 elements has about 900 slow
+// elements, one wave's share about 57.
 //
 // Queue overflow (more slow elements than the queue holds, which hash words
-// practically never produce): a wave whose group of entries does not fit
-// stops queueing, marks the positions it reserved as empty, and after the
-// drain redoes the fast test over the rest of its tile and resolves its own
-// slow elements in-lane.
+// practically never produce): an element that finds the queue full is
+// resolved at once by its own lane, which stored its placeholder.
 
 constexpr uint32_t BSTEP = 256;    // elements per wave step
 constexpr uint32_t BGROUP = 4;     // steps per queue flush
 constexpr uint32_t BQ = 2048;      // block queue capacity (entries)
-constexpr uint32_t QEMPTY = 0xFFFFFFFFu;
 
 // Tables of the fast and slow paths, in LDS.
 struct LdsTabs {
@@ -435,6 +432,7 @@ struct LdsTabs {
 struct BlockLds {
   LdsTabs t;
   uint32_t cnt;
+  uint32_t next;             // next group of the workgroup tile to stream
   uint32_t q[BQ];            // element offsets from the block base
 };
 
@@ -485,9 +483,10 @@ DEV double resolve(const Job &J, const LdsTabs &L, const DevTables *T, double r,
       const uint64_t W = wordk<KIND>(T, J.seed, s, v, d);
       i = (uint32_t)(W >> 57);
       neg = (uint32_t)(W >> 56) & 1;
-      const uint64_t j = (W >> 3) & MASK53;
+      const uint32_t jh = j_hi((uint32_t)(W >> 32)), jl = j_lo((uint32_t)(W >> 32), (uint32_t)W);
+      const uint64_t j = ((uint64_t)jh << 32) | jl;
       const Fast64 f = L.f64[i];
-      x = to_f64(j) * f.w;
+      x = to_f64(jh, jl) * f.w;
       if (j < f.k) {
         z = neg ? -x : x;
         break;
@@ -686,17 +685,6 @@ DEV uint32_t step_general(const Job &J, const Fast64 *f64t, const Fast32 *f32t,
   return b4;
 }
 
-// Whether the first attempt of variate v of stream s passes the fast test.
-template <int OP, int KIND>
-DEV bool first_fast(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t s, uint64_t v) {
-  if (OP == OP_ZIG32) {
-    const uint32_t u = word32<KIND>(T, J.seed, s, v, 0);
-    return (u & 0xFFFFFFu) < L.f32[u >> 25].k;
-  }
-  const uint64_t W = wordk<KIND>(T, J.seed, s, v, 0);
-  return ((W >> 3) & MASK53) < L.f64[(uint32_t)(W >> 57)].k;
-}
-
 // Stores the resolved value z of element e (the placeholder is overwritten;
 // for mutation the placeholder is the old value).
 template <int OP>
@@ -712,134 +700,119 @@ DEV void patch_store(const Job &J, uint64_t e, double z) {
   }
 }
 
-// The steps of a wave's tile [ew, ee): fast path, stores, and the queue
-// flushes every BGROUP steps.  Returns the first element of the group where
-// queueing stopped for lack of space (ee if it never did): that group and the
-// rest of the tile are left to the overflow pass; `stored` is the end of what
-// was stored (final values for fast elements, placeholders for slow ones).
+// Resolves element e in its own lane and stores it over its placeholder
+// (queue overflow only).
 template <int OP, int KIND>
-DEV uint64_t tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneConst &LC,
-                       uint64_t b0, uint64_t ew, uint64_t ee, uint32_t qcap, uint64_t &stored) {
-  const uint32_t lane = lane_id();
-  const bool multi = J.n_streams != 1;
-  uint32_t s = J.s0;
-  uint64_t rr = ew;
-  if (multi) {
-    uint64_t v;
-    split(J, ew, s, v);
-    s = uni(s);
-    rr = uni64(v - J.first);
-  }
-  uint32_t bits = 0, sub = 0;
-  uint64_t gbase = ew;   // first element of the current group
-  uint64_t stop = ee;
-  for (uint64_t ec = ew; ec < ee; ec += BSTEP) {
-    double x[4];
-    float xf[4];
-    uint32_t b4;
-    const bool full = ec + BSTEP <= ee;
-    if (!multi || rr + BSTEP <= J.n_per) {
-      const uint64_t vc = J.first + rr;
-      if (full)
-        b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ee, s, vc, x, xf);
-      else
-        b4 = step_regs<OP, KIND, false>(J, L.t.f64, L.t.f32, T, LC, ec, ee, s, vc, x, xf);
-    } else {
-      b4 = step_general<OP, KIND>(J, L.t.f64, L.t.f32, T, ec, ee, x, xf);
-    }
-    if (full)
-      step_store<OP, true>(J, ec, ee, x, xf);
-    else
-      step_store<OP, false>(J, ec, ee, x, xf);
-    {
-      bits |= b4 << (4 * sub);
-      if (++sub == BGROUP || !full || ec + BSTEP >= ee) {
-        // a wave-wide exclusive prefix of the slow counts (0..16 per lane)
-        const uint32_t c = __builtin_popcount(bits);
-        const uint64_t B0 = __builtin_amdgcn_ballot_w64((c & 1) != 0);
-        const uint64_t B1 = __builtin_amdgcn_ballot_w64((c & 2) != 0);
-        const uint64_t B2 = __builtin_amdgcn_ballot_w64((c & 4) != 0);
-        const uint64_t B3 = __builtin_amdgcn_ballot_w64((c & 8) != 0);
-        const uint64_t B4 = __builtin_amdgcn_ballot_w64((c & 16) != 0);
-        const uint32_t tot = (uint32_t)__popcll(B0) + 2 * (uint32_t)__popcll(B1) +
-                             4 * (uint32_t)__popcll(B2) + 8 * (uint32_t)__popcll(B3) +
-                             16 * (uint32_t)__popcll(B4);
-        if (tot) {
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(&L.cnt, tot);
-          base = uni(base);
-          if (base + tot <= qcap) {
-            uint32_t p = base + prefix_below(B0) + 2 * prefix_below(B1) +
-                         4 * prefix_below(B2) + 8 * prefix_below(B3) + 16 * prefix_below(B4);
-            while (bits) {
-              const uint32_t b = __builtin_ctz(bits);
-              bits &= bits - 1;
-              L.q[p++] = (uint32_t)(slot_elem<OP>(gbase + (b >> 2) * BSTEP, lane, b & 3) - b0);
-            }
-          } else {
-            // does not fit: mark the reserved positions below qcap empty and
-            // leave this group and the rest of the tile to the overflow pass
-            for (uint32_t p = base + lane; p < base + tot && p < qcap; p += 64) L.q[p] = QEMPTY;
-            stop = gbase;
-            stored = full ? ec + BSTEP : ee;
-            break;
-          }
-        }
-        bits = 0;
-        sub = 0;
-        gbase = ec + BSTEP;
-      }
-    }
-    rr += BSTEP;
-    if (multi)
-      while (rr >= J.n_per) {
-        rr -= J.n_per;
-        ++s;
-      }
-  }
-  return stop;
+DEV void resolve_store(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t dmax,
+                       uint64_t e, uint32_t *flags) {
+  uint32_t se;
+  uint64_t ve;
+  split(J, e, se, ve);
+  bool budget = false;
+  patch_store<OP>(J, e, resolve<OP, KIND>(J, L, T, T->r, dmax, se, ve, budget));
+  if (budget) raise_flag(flags, ZG_FLAG_BUDGET);
 }
 
-// One workgroup tile [b0, b1) of job J (wave w: [b0 + w tile, + tile)):
-// streaming pass, one barrier, pooled drain, overflow pass; `head` elements
-// before b0 (the unaligned start of the job) are resolved too when non-zero.
-// The tables in L are loaded; the caller separates consecutive calls with a
-// barrier (the queue count is reset here, before the first barrier).
+// The streaming pass over a workgroup tile [b0, b1): the waves take groups
+// of BGROUP steps (1024 elements) in turn from a shared counter, so that
+// they all run out of work together.  Per step: fast path and stores; per
+// group, each lane with slow elements appends them to the workgroup queue
+// (one LDS atomic per such lane; queue order is immaterial, every result is
+// keyed by its element).  Elements that do not fit in the queue are resolved
+// by their own lane at once, after its own store of the same address.
+template <int OP, int KIND>
+DEV void tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneConst &LC,
+                   uint64_t b0, uint64_t b1, uint32_t qcap, uint32_t dmax, uint32_t *flags) {
+  constexpr uint32_t GE = BGROUP * BSTEP;
+  const uint32_t lane = lane_id();
+  const bool multi = J.n_streams != 1;
+  for (;;) {
+    uint32_t g = 0;
+    if (lane == 0) g = atomicAdd(&L.next, 1u);
+    const uint32_t gofs = uni(g) * GE;   // the group's first element, from b0
+    const uint64_t gs = b0 + gofs;
+    if (gs >= b1) break;
+    const uint64_t ge = gs + GE < b1 ? gs + GE : b1;
+    uint32_t s = J.s0;
+    uint64_t rr = gs;
+    if (multi) {
+      uint64_t v;
+      split(J, gs, s, v);
+      s = uni(s);
+      rr = uni64(v - J.first);
+    }
+    uint32_t bits = 0, sub = 0;
+    for (uint64_t ec = gs; ec < ge; ec += BSTEP, ++sub) {
+      double x[4];
+      float xf[4];
+      uint32_t b4;
+      const bool full = ec + BSTEP <= ge;
+      if (!multi || rr + BSTEP <= J.n_per) {
+        const uint64_t vc = J.first + rr;
+        if (full)
+          b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, x, xf);
+        else
+          b4 = step_regs<OP, KIND, false>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, x, xf);
+      } else {
+        b4 = step_general<OP, KIND>(J, L.t.f64, L.t.f32, T, ec, ge, x, xf);
+      }
+      if (full)
+        step_store<OP, true>(J, ec, ge, x, xf);
+      else
+        step_store<OP, false>(J, ec, ge, x, xf);
+      bits |= b4 << (4 * sub);
+      rr += BSTEP;
+      if (multi)
+        while (rr >= J.n_per) {
+          rr -= J.n_per;
+          ++s;
+        }
+    }
+    if (bits) {
+      uint32_t p = atomicAdd(&L.cnt, (uint32_t)__builtin_popcount(bits));
+      do {
+        const uint32_t b = __builtin_ctz(bits);
+        bits &= bits - 1;
+        const uint32_t off = gofs + (b >> 2) * BSTEP + (uint32_t)slot_elem<OP>(0, lane, b & 3);
+        if (p < qcap)
+          L.q[p] = off;
+        else
+          resolve_store<OP, KIND>(J, L.t, T, dmax, b0 + off, flags);
+        ++p;
+      } while (bits);
+    }
+  }
+}
+
+// One workgroup tile [b0, b1) of job J: streaming pass, one barrier, pooled
+// drain; `head` elements before b0 (the unaligned start of the job) are
+// resolved too when non-zero.  The tables in L are loaded; the caller
+// separates consecutive calls with a barrier (the queue count and the group
+// counter are reset here, before the first barrier).
 template <int OP, int KIND>
 DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
-                   const LaneConst &LC, double r, uint32_t dmax, uint32_t tile, uint64_t b0,
+                   const LaneConst &LC, double r, uint32_t dmax, uint32_t *flags, uint64_t b0,
                    uint64_t b1, uint32_t head, uint32_t qcap, bool &budget) {
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wave = uni(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
-  if (threadIdx.x == 0) L.cnt = 0;
+  if (threadIdx.x == 0) {
+    L.cnt = 0;
+    L.next = 0;
+  }
   __syncthreads();
-  const uint64_t ew = uni64(b0 + (uint64_t)wave * tile < b1 ? b0 + (uint64_t)wave * tile : b1);
-  const uint64_t ee = uni64(ew + tile < b1 ? ew + tile : b1);
-  uint64_t stop = ee, stored = ee;
-  if (ew < ee) stop = tile_pass<OP, KIND>(J, L, T, LC, b0, ew, ee, qcap, stored);
+  tile_pass<OP, KIND>(J, L, T, LC, b0, b1, qcap, dmax, flags);
   __syncthreads();   // placeholders before patches; the queue is complete
   const uint32_t n = uni(L.cnt < qcap ? L.cnt : qcap);
   for (uint32_t cb = wave * 64; cb < n; cb += nw * 64) {
     const uint32_t p = cb + lane;
-    const uint32_t ent = p < n ? L.q[p] : QEMPTY;
-    if (ent != QEMPTY) {
-      const uint64_t e = b0 + ent;
+    if (p < n) {
+      const uint64_t e = b0 + L.q[p];
       uint32_t se;
       uint64_t ve;
       split(J, e, se, ve);
       patch_store<OP>(J, e, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
     }
-  }
-  // overflow pass: the elements of [stop, ee) that are not final yet, each
-  // from its first draw (the barrier above orders the stores of the main pass
-  // before these)
-  for (uint64_t e = stop + lane; e < ee; e += 64) {
-    uint32_t se;
-    uint64_t ve;
-    split(J, e, se, ve);
-    if (e < stored && first_fast<OP, KIND>(J, L.t, T, se, ve)) continue;
-    patch_store<OP>(J, e, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
   }
   // the elements before the first aligned one (wave 0)
   if (wave == 0 && lane < head) {
@@ -866,7 +839,7 @@ __global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t b0 = uni64(t * bt + head);
     const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
-    zig_block<OP, KIND>(J, L, T, LC, r, dmax, tile, b0, b1, t == 0 ? head : 0u, qcap, budget);
+    zig_block<OP, KIND>(J, L, T, LC, r, dmax, flags, b0, b1, t == 0 ? head : 0u, qcap, budget);
     __syncthreads();   // the next tile resets the queue
   }
   if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane_id() == 0)
@@ -1002,8 +975,7 @@ __global__ __launch_bounds__(1024) void k_bzig(DevRequest *R, const BatchHeader 
       const uint64_t bt = (uint64_t)rq.tile * nw;
       const uint64_t b0 = uni64(rq.head + j * bt);
       const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
-      zig_block<OP, KIND>(J, L, T, LC, r, dmax, rq.tile, b0, b1, j == 0 ? rq.head : 0u, BQ,
-                          budget);
+      zig_block<OP, KIND>(J, L, T, LC, r, dmax, flags, b0, b1, j == 0 ? rq.head : 0u, BQ, budget);
     }
     __syncthreads();   // the next tile resets the queue
   }
