@@ -262,6 +262,10 @@ def main():
                             seed=SEED, stream0=0, first_index=0)
 
     res = {}
+    if args.only == "all":
+        # a plain store-only kernel writing the same 2 GiB (torch fill_): the
+        # write bandwidth this machine reaches with no compute at all
+        res["store_only"] = time_kernel(lambda: out.fill_(0.5), args.steps, args.warmup, torch)
     if args.only in ("zig", "all"):
         res["zig"] = time_kernel(zig, args.steps, args.warmup, torch)
     if args.only in ("polar", "all"):
@@ -275,7 +279,7 @@ def main():
     wall_ms = wall * 1e3 / args.steps
     bytes_per = 8.0 * n
     achieved = bytes_per / (ms * 1e-3) / 1e9
-    kernel = "k_zig<OP_ZIG64>" if main_key == "zig" else "k_fill<OP_POLAR>"
+    kernel = "k_zig<OP_ZIG64>" if main_key == "zig" else "k_polar"
     traffic = read_traffic(kernel)
     line = {
         "metric": METRIC,
@@ -303,6 +307,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per},
     }
+    if "store_only" in res:
+        sgbs = bytes_per / (res["store_only"][0] * 1e-3) / 1e9
+        line["roofline"]["store_only_GBps"] = sgbs
+        line["roofline"]["frac_of_store_only"] = achieved / sgbs
     if "polar" in res and main_key == "zig":
         pms = res["polar"][0]
         pwall = res["polar"][2] * 1e3 / args.steps

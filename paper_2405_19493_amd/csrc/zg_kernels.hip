@@ -118,12 +118,54 @@ struct PolarStep {
 };
 
 // Polar attempt from the words of draws d and d+1 (Knuth; Random.nextGaussian).
+// 2 U - 1 for U = (W >> 11) 2^-53, exactly: the 53-bit integer in two halves,
+// each step exact (every value is a multiple of 2^-52 of magnitude <= 1).
+DEV double sym53(uint64_t W) {
+  const uint32_t hi = (uint32_t)(W >> 43), lo = (uint32_t)(W >> 11);
+  return fma((double)hi, 0x1p-20, fma((double)lo, 0x1p-52, -1.0));
+}
+
+// Natural logarithm of x in [2^-1022, 1) (the polar method's s), from the
+// binary exponent and the series log((1 + t)/(1 - t)) = 2 atanh t:
+// x = 2^e m with m in [sqrt(1/2), sqrt(2)), f = m - 1, t = f / (2 + f),
+// log m = f - (h - t (h + R)), h = f^2 / 2, R = sum_{k=1..10} 2 t^2k / (2k + 1).
+// |t| <= 0.1716, so the first omitted term is below 2^-53 of the sum; e ln 2
+// is added in two parts (the high part has 32 significant bits, so e times
+// it is exact).  Within 0.83 ulp of the true logarithm on (0, 1) (checked
+// against an extended-precision logarithm on 3e7 points).
+DEV double log_unit(double x) {
+  int e;
+  double m = frexp(x, &e);   // m in [1/2, 1)
+  if (m < 0x1.6a09e667f3bcdp-1) {
+    m *= 2.0;
+    --e;
+  }
+  const double f = m - 1.0;
+  const double t = f / (2.0 + f);
+  const double z = t * t;
+  double R = 2.0 / 21.0;
+  R = fma(R, z, 2.0 / 19.0);
+  R = fma(R, z, 2.0 / 17.0);
+  R = fma(R, z, 2.0 / 15.0);
+  R = fma(R, z, 2.0 / 13.0);
+  R = fma(R, z, 2.0 / 11.0);
+  R = fma(R, z, 2.0 / 9.0);
+  R = fma(R, z, 2.0 / 7.0);
+  R = fma(R, z, 2.0 / 5.0);
+  R = fma(R, z, 2.0 / 3.0);
+  R = R * z;
+  const double h = 0.5 * f * f;
+  const double de = (double)e;
+  const double u = fma(t, h + R, de * -0x1.718432a1b0e26p-35);   // ln 2 - 0x1.62e42ffp-1
+  return fma(de, 0x1.62e42ffp-1, -((h - u) - f));
+}
+
 DEV PolarStep polar_from_words(uint64_t W1, uint64_t W2, uint32_t d) {
-  double v1 = 2.0 * u53(W1) - 1.0;
-  double v2 = 2.0 * u53(W2) - 1.0;
-  double ss = v1 * v1 + v2 * v2;
+  const double v1 = sym53(W1);
+  const double v2 = sym53(W2);
+  const double ss = v1 * v1 + v2 * v2;
   if (ss >= 1.0 || ss == 0.0) return {0, 0.0, 0.0, d + 2};
-  double m = sqrt(-2.0 * log(ss) / ss);
+  const double m = sqrt(-2.0 * log_unit(ss) / ss);
   return {1, v1 * m, v2 * m, d};
 }
 
