@@ -85,7 +85,6 @@ DEV double u53(uint64_t W) { return (double)(W >> 11) * 0x1p-53; }
 DEV double u53p(uint64_t W) { return (double)((W >> 11) + 1) * 0x1p-53; }
 
 DEV double nan64() { return __longlong_as_double(0x7FF8000000000000ll); }
-DEV float nan32() { return __int_as_float(0x7FC00000); }
 
 DEV double flip(double x, uint64_t neg) {
   return __longlong_as_double(__double_as_longlong(x) ^ (long long)(neg << 63));
@@ -117,7 +116,6 @@ struct PolarStep {
   uint32_t next_d;
 };
 
-// Polar attempt from the words of draws d and d+1 (Knuth; Random.nextGaussian).
 // 2 U - 1 for U = (W >> 11) 2^-53, exactly: the 53-bit integer in two halves,
 // each step exact (every value is a multiple of 2^-52 of magnitude <= 1).
 DEV double sym53(uint64_t W) {
@@ -128,11 +126,13 @@ DEV double sym53(uint64_t W) {
 // Natural logarithm of x in [2^-1022, 1) (the polar method's s), from the
 // binary exponent and the series log((1 + t)/(1 - t)) = 2 atanh t:
 // x = 2^e m with m in [sqrt(1/2), sqrt(2)), f = m - 1, t = f / (2 + f),
-// log m = f - (h - t (h + R)), h = f^2 / 2, R = sum_{k=1..10} 2 t^2k / (2k + 1).
-// |t| <= 0.1716, so the first omitted term is below 2^-53 of the sum; e ln 2
-// is added in two parts (the high part has 32 significant bits, so e times
-// it is exact).  Within 0.83 ulp of the true logarithm on (0, 1) (checked
-// against an extended-precision logarithm on 3e7 points).
+// log m = f - h + t (h + R), h = f^2 / 2, R = sum_{k=1..10} 2 t^2k / (2k + 1).
+// |t| <= 0.1716, so the first omitted term is below 2^-53 of the sum.  The
+// large terms are summed with their rounding errors carried: h as h + hl
+// (exact), f - h and e ln2_hi + (f - h) by error-free two-sums; ln 2 is split
+// so that e ln2_hi is exact (32 significant bits).  Within 0.67 ulp of the
+// true logarithm on (0, 1) (checked against an extended-precision logarithm
+// on 3e7 points).
 DEV double log_unit(double x) {
   int e;
   double m = frexp(x, &e);   // m in [1/2, 1)
@@ -154,12 +154,20 @@ DEV double log_unit(double x) {
   R = fma(R, z, 2.0 / 5.0);
   R = fma(R, z, 2.0 / 3.0);
   R = R * z;
-  const double h = 0.5 * f * f;
+  const double hf = 0.5 * f;
+  const double h = hf * f;
+  const double hl = fma(hf, f, -h);   // h + hl = f^2 / 2 exactly
+  const double a = f - h;             // |h| <= 0.15 |f|: a + ae = f - h exactly
+  const double ae = (f - a) - h;
   const double de = (double)e;
-  const double u = fma(t, h + R, de * -0x1.718432a1b0e26p-35);   // ln 2 - 0x1.62e42ffp-1
-  return fma(de, 0x1.62e42ffp-1, -((h - u) - f));
+  const double big = de * 0x1.62e42ffp-1;   // e ln2_hi, exact
+  const double small = ((t * (h + R) - hl) + ae) + de * -0x1.718432a1b0e26p-35;   // e ln2_lo
+  const double r1 = big + a;
+  const double r1e = e != 0 ? (big - r1) + a : (a - r1) + big;   // the larger term first
+  return r1 + (r1e + small);
 }
 
+// Polar attempt from the words of draws d and d+1 (Knuth; Random.nextGaussian).
 DEV PolarStep polar_from_words(uint64_t W1, uint64_t W2, uint32_t d) {
   const double v1 = sym53(W1);
   const double v2 = sym53(W2);
