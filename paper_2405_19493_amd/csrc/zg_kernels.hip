@@ -6,8 +6,10 @@
 //   with x = j w[i] (one multiply and one compare per lane) -> coalesced
 //   128-bit stores.  Elements that fail the fast test (about 2.8% of them)
 //   are appended to one LDS queue per workgroup; the queue is drained 64
-//   entries at a time, each lane running the wedge / tail / retry loop of
-//   one queued variate, so the rare slow path does not diverge the fast one.
+//   entries at a time, each lane taking one queued variate through its
+//   wedge test (the few left undecided, and the base-strip tails, are
+//   finished later in full rounds of their own), so the rare slow path does
+//   not diverge the fast one.
 //   Every variate is a pure function of its index, so the launch shape, the
 //   queue order and the batch layout never change the bits.
 //
@@ -458,10 +460,14 @@ DEV void polar_tile(const Job &J, const PolarCtx &C, const LaneConst &LC, uint32
 // candidate, or for mutation the old value).  The slow elements of all waves
 // go into one LDS queue (offsets from the tile base).  After one workgroup
 // barrier, which also orders every placeholder store before any patch, the
-// waves drain the pooled queue 64 entries at a time, each lane running the
-// whole attempt loop of one variate and storing its value.  Pooling keeps the
-// drain rounds nearly full: a tile of 16 x 2048 elements has about 900 slow
-// elements, one wave's share about 57.
+// waves drain the pooled queue 64 entries at a time, each lane taking one
+// variate through its wedge test and, on rejection, the fast test of its
+// next attempt, and storing the value when that decides it.  The 3-4% left
+// undecided, and the base-strip attempts (the tail, with its logarithm), go
+// to a retry queue that later rounds finish with the whole attempt loop:
+// whole rounds of 64 at the start of the next tile of the same job, the
+// rest at the end.  Pooling keeps the drain rounds nearly full: a tile of
+// 16 x 2048 elements has about 900 slow elements, one wave's share about 57.
 //
 // Queue overflow (more slow elements than the queue holds, which hash words
 // practically never produce): an element that finds the queue full is
@@ -479,11 +485,18 @@ struct LdsTabs {
   double w24d[ZG_LAYERS];    // FP32 mode: w24 as a double
 };
 
+constexpr uint32_t RQ = 512;       // retry queue capacity (entries)
+constexpr uint32_t ENT_D = 48;     // retry entry: element | first draw << ENT_D
+constexpr uint64_t ENT_E = (1ull << ENT_D) - 1;
+
 struct BlockLds {
   LdsTabs t;
   uint32_t cnt;
   uint32_t next;             // next group of the workgroup tile to stream
+  uint32_t rcnt;             // retry queue count
+  uint32_t rbeg, rtake;      // retries taken at the start of a tile: [rbeg, + rtake)
   uint32_t q[BQ];            // element offsets from the block base
+  uint64_t rq[RQ];           // variates left undecided by a first drain step
 };
 
 // Loads the tables an op needs (whole block; no barrier).
@@ -506,8 +519,7 @@ DEV void load_tabs(const DevTables *T, LdsTabs &L) {
 // the canonical NaN when the draw budget runs out.
 template <int OP, int KIND>
 DEV double resolve(const Job &J, const LdsTabs &L, const DevTables *T, double r, uint32_t dmax,
-                   uint32_t s, uint64_t v, bool &budget) {
-  uint32_t d = 0;
+                   uint32_t s, uint64_t v, bool &budget, uint32_t d = 0) {
   double z;
   for (;;) {
     if (d >= dmax) {
@@ -763,6 +775,116 @@ DEV void resolve_store(const Job &J, const LdsTabs &L, const DevTables *T, uint3
   if (budget) raise_flag(flags, ZG_FLAG_BUDGET);
 }
 
+// Attempt d of variate v of stream s: the layer i, the sign, and x (the
+// attempt's abscissa); returns whether the attempt passes the fast test,
+// and then z is its value (the same arithmetic as resolve).
+template <int OP, int KIND>
+DEV bool attempt_at(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t s, uint64_t v,
+                    uint32_t d, uint32_t &i, uint32_t &neg, double &x, double &z) {
+  if (OP == OP_ZIG32) {
+    const uint32_t u = word32<KIND>(T, J.seed, s, v, d);
+    i = u >> 25;
+    neg = (u >> 24) & 1;
+    const uint32_t j = u & 0xFFFFFFu;
+    const Fast32 f = L.f32[i];
+    const float xf = (float)j * f.w;
+    z = (double)(neg ? -xf : xf);
+    x = (double)j * L.w24d[i];
+    return j < f.k;
+  } else {
+    const uint64_t W = wordk<KIND>(T, J.seed, s, v, d);
+    i = (uint32_t)(W >> 57);
+    neg = (uint32_t)(W >> 56) & 1;
+    const uint32_t jh = j_hi((uint32_t)(W >> 32)), jl = j_lo((uint32_t)(W >> 32), (uint32_t)W);
+    const Fast64 f = L.f64[i];
+    x = to_f64(jh, jl) * f.w;
+    z = neg ? -x : x;
+    return (((uint64_t)jh << 32) | jl) < f.k;
+  }
+}
+
+// First drain step of slow element e: its attempt 0 in a wedge (and, on
+// rejection, the fast test of attempt 2).  A variate still undecided after
+// that, or whose attempt 0 falls in the base strip (the tail's logarithm),
+// goes to the retry queue, where full rounds of 64 finish such variates
+// together; with the retry queue full the lane finishes it itself.  The
+// steps, draws and arithmetic are those of resolve.
+template <int OP, int KIND>
+DEV void drain_first(const Job &J, BlockLds &L, const DevTables *T, double r, uint32_t dmax,
+                     uint64_t e, bool &budget) {
+  uint32_t s;
+  uint64_t v;
+  split(J, e, s, v);
+  uint32_t i, neg, d = 0;
+  double x, z;
+  bool done = attempt_at<OP, KIND>(J, L.t, T, s, v, 0, i, neg, x, z);
+  if (d >= dmax) {
+    budget = true;
+    z = nan64();
+    done = true;
+  } else if (!done && i != 0) {
+    if (d + 1 >= dmax) {
+      budget = true;
+      z = nan64();
+      done = true;
+    } else {
+      const double u = u53(wordk<KIND>(T, J.seed, s, v, d + 1));
+      const double2 yd = L.t.yd[i];
+      if (yd.x + u * yd.y < exp(-0.5 * (x * x))) {
+        z = neg ? -x : x;
+        done = true;
+      } else {
+        d += 2;
+        if (d >= dmax) {
+          budget = true;
+          z = nan64();
+          done = true;
+        } else {
+          done = attempt_at<OP, KIND>(J, L.t, T, s, v, d, i, neg, x, z);
+        }
+      }
+    }
+  }
+  if (!done) {
+    const uint32_t p = atomicAdd(&L.rcnt, 1u);
+    if (p < RQ) {
+      L.rq[p] = e | ((uint64_t)d << ENT_D);
+      return;
+    }
+    z = resolve<OP, KIND>(J, L.t, T, r, dmax, s, v, budget, d);
+  }
+  patch_store<OP>(J, e, z);
+}
+
+// A round over retry entries [p0, p0 + n) (n <= 64), one per lane, each
+// finished by resolve from its recorded draw.
+template <int OP, int KIND>
+DEV void retry_round(const Job &J, const BlockLds &L, const DevTables *T, double r, uint32_t dmax,
+                     uint32_t p0, uint32_t n, bool &budget) {
+  const uint32_t lane = lane_id();
+  if (lane < n) {
+    const uint64_t ent = L.rq[p0 + lane];
+    const uint64_t e = ent & ENT_E;
+    uint32_t s;
+    uint64_t v;
+    split(J, e, s, v);
+    patch_store<OP>(J, e, resolve<OP, KIND>(J, L.t, T, r, dmax, s, v, budget,
+                                            (uint32_t)(ent >> ENT_D)));
+  }
+}
+
+// Finishes every entry of the retry queue (whole workgroup; the caller
+// brackets this with barriers).
+template <int OP, int KIND>
+DEV void retry_all(const Job &J, BlockLds &L, const DevTables *T, double r, uint32_t dmax,
+                   bool &budget) {
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const uint32_t n = uni(L.rcnt < RQ ? L.rcnt : RQ);
+  for (uint32_t b = wave * 64; b < n; b += nw * 64)
+    retry_round<OP, KIND>(J, L, T, r, dmax, b, n - b < 64 ? n - b : 64, budget);
+}
+
 // The streaming pass over a workgroup tile [b0, b1): the waves take groups
 // of BGROUP steps (1024 elements) in turn from a shared counter, so that
 // they all run out of work together.  Per step: fast path and stores; per
@@ -842,27 +964,34 @@ DEV void tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneCons
 template <int OP, int KIND>
 DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
                    const LaneConst &LC, double r, uint32_t dmax, uint32_t *flags, uint64_t b0,
-                   uint64_t b1, uint32_t head, uint32_t qcap, bool &budget) {
+                   uint64_t b1, uint32_t head, uint32_t qcap, bool carry, bool &budget) {
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wave = uni(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) {
     L.cnt = 0;
     L.next = 0;
+    // retries carried from earlier tiles (same job): whole rounds, one per wave
+    const uint32_t rc = carry ? (L.rcnt < RQ ? L.rcnt : RQ) : 0;
+    uint32_t take = rc / 64 * 64;
+    if (take > nw * 64) take = nw * 64;
+    L.rtake = take;
+    L.rbeg = rc - take;
+    L.rcnt = rc - take;
   }
   __syncthreads();
+  if (wave * 64 < uni(L.rtake))
+    retry_round<OP, KIND>(J, L, T, r, dmax, uni(L.rbeg) + wave * 64, 64, budget);
   tile_pass<OP, KIND>(J, L, T, LC, b0, b1, qcap, dmax, flags);
   __syncthreads();   // placeholders before patches; the queue is complete
   const uint32_t n = uni(L.cnt < qcap ? L.cnt : qcap);
   for (uint32_t cb = wave * 64; cb < n; cb += nw * 64) {
     const uint32_t p = cb + lane;
-    if (p < n) {
-      const uint64_t e = b0 + L.q[p];
-      uint32_t se;
-      uint64_t ve;
-      split(J, e, se, ve);
-      patch_store<OP>(J, e, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
-    }
+    if (p < n) drain_first<OP, KIND>(J, L, T, r, dmax, b0 + L.q[p], budget);
+  }
+  if (!carry) {
+    __syncthreads();   // the retry queue is complete
+    retry_all<OP, KIND>(J, L, T, r, dmax, budget);
   }
   // the elements before the first aligned one (wave 0)
   if (wave == 0 && lane < head) {
@@ -885,13 +1014,17 @@ __global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict
   const double r = T->r;
   const LaneConst LC = lane_constants<OP, KIND>(T);
   bool budget = false;
+  if (threadIdx.x == 0) L.rcnt = 0;
   const uint64_t bt = (uint64_t)tile * (blockDim.x >> 6);
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t b0 = uni64(t * bt + head);
     const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
-    zig_block<OP, KIND>(J, L, T, LC, r, dmax, flags, b0, b1, t == 0 ? head : 0u, qcap, budget);
+    zig_block<OP, KIND>(J, L, T, LC, r, dmax, flags, b0, b1, t == 0 ? head : 0u, qcap, true,
+                        budget);
     __syncthreads();   // the next tile resets the queue
   }
+  __syncthreads();
+  retry_all<OP, KIND>(J, L, T, r, dmax, budget);
   if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane_id() == 0)
     raise_flag(flags, ZG_FLAG_BUDGET);
 }
@@ -1025,7 +1158,8 @@ __global__ __launch_bounds__(1024) void k_bzig(DevRequest *R, const BatchHeader 
       const uint64_t bt = (uint64_t)rq.tile * nw;
       const uint64_t b0 = uni64(rq.head + j * bt);
       const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
-      zig_block<OP, KIND>(J, L, T, LC, r, dmax, flags, b0, b1, j == 0 ? rq.head : 0u, BQ, budget);
+      zig_block<OP, KIND>(J, L, T, LC, r, dmax, flags, b0, b1, j == 0 ? rq.head : 0u, BQ, false,
+                          budget);
     }
     __syncthreads();   // the next tile resets the queue
   }
