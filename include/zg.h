@@ -248,8 +248,8 @@ zg_status zg_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, uint64_t 
  * 0 (one workgroup per tile) or the most persistent workgroups per CU (capped
  * by occupancy), and queue_cap: the workgroup's slow-path queue
  * capacity of the plain ziggurat fills (0 = the built-in maximum of 2048;
- * smaller values only serve to exercise the overflow path).  Any shape gives
- * the same bits. */
+ * smaller values, which also cap the retry queue below its 512 entries, only
+ * serve to exercise the overflow paths).  Any shape gives the same bits. */
 typedef struct zg_tune {
   uint32_t tile;
   uint32_t waves_per_block;

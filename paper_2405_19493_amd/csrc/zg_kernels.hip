@@ -806,12 +806,12 @@ DEV bool attempt_at(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t
 // First drain step of slow element e: its attempt 0 in a wedge (and, on
 // rejection, the fast test of attempt 2).  A variate still undecided after
 // that, or whose attempt 0 falls in the base strip (the tail's logarithm),
-// goes to the retry queue, where full rounds of 64 finish such variates
-// together; with the retry queue full the lane finishes it itself.  The
-// steps, draws and arithmetic are those of resolve.
+// goes to the retry queue (capacity rqc <= RQ), where full rounds of 64
+// finish such variates together; with the retry queue full the lane
+// finishes it itself.  The steps, draws and arithmetic are those of resolve.
 template <int OP, int KIND>
 DEV void drain_first(const Job &J, BlockLds &L, const DevTables *T, double r, uint32_t dmax,
-                     uint64_t e, bool &budget) {
+                     uint32_t rqc, uint64_t e, bool &budget) {
   uint32_t s;
   uint64_t v;
   split(J, e, s, v);
@@ -847,7 +847,7 @@ DEV void drain_first(const Job &J, BlockLds &L, const DevTables *T, double r, ui
   }
   if (!done) {
     const uint32_t p = atomicAdd(&L.rcnt, 1u);
-    if (p < RQ) {
+    if (p < rqc) {
       L.rq[p] = e | ((uint64_t)d << ENT_D);
       return;
     }
@@ -873,14 +873,14 @@ DEV void retry_round(const Job &J, const BlockLds &L, const DevTables *T, double
   }
 }
 
-// Finishes every entry of the retry queue (whole workgroup; the caller
-// brackets this with barriers).
+// Finishes every entry of the retry queue (capacity rqc; whole workgroup,
+// the caller brackets this with barriers).
 template <int OP, int KIND>
 DEV void retry_all(const Job &J, BlockLds &L, const DevTables *T, double r, uint32_t dmax,
-                   bool &budget) {
+                   uint32_t rqc, bool &budget) {
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wave = uni(threadIdx.x >> 6);
-  const uint32_t n = uni(L.rcnt < RQ ? L.rcnt : RQ);
+  const uint32_t n = uni(L.rcnt < rqc ? L.rcnt : rqc);
   for (uint32_t b = wave * 64; b < n; b += nw * 64)
     retry_round<OP, KIND>(J, L, T, r, dmax, b, n - b < 64 ? n - b : 64, budget);
 }
@@ -968,11 +968,12 @@ DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wave = uni(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
+  const uint32_t rqc = qcap < RQ ? qcap : RQ;   // a forced small queue caps both
   if (threadIdx.x == 0) {
     L.cnt = 0;
     L.next = 0;
     // retries carried from earlier tiles (same job): whole rounds, one per wave
-    const uint32_t rc = carry ? (L.rcnt < RQ ? L.rcnt : RQ) : 0;
+    const uint32_t rc = carry ? (L.rcnt < rqc ? L.rcnt : rqc) : 0;
     uint32_t take = rc / 64 * 64;
     if (take > nw * 64) take = nw * 64;
     L.rtake = take;
@@ -987,11 +988,11 @@ DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
   const uint32_t n = uni(L.cnt < qcap ? L.cnt : qcap);
   for (uint32_t cb = wave * 64; cb < n; cb += nw * 64) {
     const uint32_t p = cb + lane;
-    if (p < n) drain_first<OP, KIND>(J, L, T, r, dmax, b0 + L.q[p], budget);
+    if (p < n) drain_first<OP, KIND>(J, L, T, r, dmax, rqc, b0 + L.q[p], budget);
   }
   if (!carry) {
     __syncthreads();   // the retry queue is complete
-    retry_all<OP, KIND>(J, L, T, r, dmax, budget);
+    retry_all<OP, KIND>(J, L, T, r, dmax, rqc, budget);
   }
   // the elements before the first aligned one (wave 0)
   if (wave == 0 && lane < head) {
@@ -1024,7 +1025,7 @@ __global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict
     __syncthreads();   // the next tile resets the queue
   }
   __syncthreads();
-  retry_all<OP, KIND>(J, L, T, r, dmax, budget);
+  retry_all<OP, KIND>(J, L, T, r, dmax, qcap < RQ ? qcap : RQ, budget);
   if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane_id() == 0)
     raise_flag(flags, ZG_FLAG_BUDGET);
 }

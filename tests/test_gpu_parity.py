@@ -204,10 +204,10 @@ def test_errors_are_reported(ctx, zg):
 
 @pytest.mark.parametrize("qcap", [1, 16, 200])
 def test_queue_overflow_path(ctx, zg, qcap):
-    """A workgroup queue too small for its slow elements: the overflowing
-    waves resolve the rest of their tiles themselves.  Output must not change
-    (checked against the default capacity bit for bit, and against the
-    oracle)."""
+    """A workgroup queue too small for its slow elements (the same cap
+    applies to the retry queue): elements that find a queue full are resolved
+    by their own lane.  Output must not change (checked against the default
+    capacity bit for bit, and against the oracle)."""
     cases = [(zg.ZG_TUNE_FILL_F64, torch.float64, 100003, 1), (zg.ZG_TUNE_FILL_F32, torch.float32, 100003, 3),
              (zg.ZG_TUNE_FILL_F64, torch.float64, 37 * 1000, 0)]
     saved = {c: ctx.zg_get_tune(c) for c in (zg.ZG_TUNE_FILL_F64, zg.ZG_TUNE_FILL_F32, zg.ZG_TUNE_MUTATE)}
