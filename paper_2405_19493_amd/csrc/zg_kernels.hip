@@ -599,11 +599,12 @@ DEV uint64_t slot_elem(uint64_t ec, uint32_t lane, uint32_t t) {
 // Fast path of one clean step into registers (x: FP64 values, or for mutation
 // old + sigma z with the old value kept where the element is slow; xf: FP32
 // values).  Elements at or beyond e_end are neither computed nor marked.
-// Returns the lane's 4 slow bits.
+// Returns the lane's 4 slow bits.  For the LCG, Sc is the state of LCG step
+// 2 lcg_index(s, vc, 0) + 1 (the first state of variate vc's word).
 template <int OP, int KIND, bool FULL>
 DEV uint32_t step_regs(const Job &J, const Fast64 *f64t, const Fast32 *f32t, const DevTables *T,
                        const LaneConst &LC, uint64_t ec, uint64_t e_end, uint32_t s, uint64_t vc,
-                       double *x, float *xf) {
+                       uint64_t Sc, double *x, float *xf) {
   constexpr bool LCG = KIND == ZG_JAVA_LCG48;
   const uint32_t lane = lane_id();
   const uint64_t seed = J.seed;
@@ -612,7 +613,6 @@ DEV uint32_t step_regs(const Job &J, const Fast64 *f64t, const Fast32 *f32t, con
     constexpr uint32_t CH = 128;
     uint64_t W[4];
     if (LCG) {
-      uint64_t Sc = lcg_jump(&T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
       W[0] = lcg_word_from(aff(LC.a[0], Sc));
       W[1] = lcg_word_from(aff(LC.a[1], Sc));
       Sc = aff(T->lcg.jump[1][1], Sc);   // 256 steps = the next 128-element chunk
@@ -666,7 +666,6 @@ DEV uint32_t step_regs(const Job &J, const Fast64 *f64t, const Fast32 *f32t, con
         uw[3] = (uint32_t)(Wc >> 32);
       }
     } else {
-      const uint64_t Sc = lcg_jump(&T->lcg, lcg_state0(seed), 2 * lcg_index(s, vc, 0) + 1);
 #pragma unroll
       for (int t = 0; t < 4; ++t) uw[t] = (uint32_t)(lcg_word_from(aff(LC.a[t], Sc)) >> 32);
     }
@@ -914,6 +913,8 @@ DEV void tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneCons
       rr = uni64(v - J.first);
     }
     uint32_t bits = 0, sub = 0;
+    uint64_t Sc = 0;   // LCG: the first state of the step's word (wave-uniform)
+    bool have = false;
     for (uint64_t ec = gs; ec < ge; ec += BSTEP, ++sub) {
       double x[4];
       float xf[4];
@@ -921,12 +922,18 @@ DEV void tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneCons
       const bool full = ec + BSTEP <= ge;
       if (!multi || rr + BSTEP <= J.n_per) {
         const uint64_t vc = J.first + rr;
+        if (KIND == ZG_JAVA_LCG48 && !have) {
+          Sc = lcg_jump(&T->lcg, lcg_state0(J.seed), 2 * lcg_index(s, vc, 0) + 1);
+          have = true;
+        }
         if (full)
-          b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, x, xf);
+          b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
         else
-          b4 = step_regs<OP, KIND, false>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, x, xf);
+          b4 = step_regs<OP, KIND, false>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
+        if (KIND == ZG_JAVA_LCG48) Sc = aff(T->lcg.jump[1][2], Sc);   // 2 x 256 LCG steps on
       } else {
         b4 = step_general<OP, KIND>(J, L.t.f64, L.t.f32, T, ec, ge, x, xf);
+        have = false;
       }
       if (full)
         step_store<OP, true>(J, ec, ge, x, xf);
@@ -938,6 +945,7 @@ DEV void tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneCons
         while (rr >= J.n_per) {
           rr -= J.n_per;
           ++s;
+          have = false;
         }
     }
     if (bits) {
