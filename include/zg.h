@@ -242,8 +242,10 @@ zg_status zg_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, uint64_t 
 
 /* ----------------------------------------------------------------- tuning */
 
-/* Launch shape of the generation kernels: elements per wave tile (f64 units;
- * multiple of 128), waves per workgroup (1..16), batch_blocks_per_cu: for the
+/* Launch shape of the generation kernels: tile, the elements per wave of a
+ * workgroup tile (f64 units; multiple of 128; a workgroup tile is tile x
+ * waves elements, which the waves of the plain fills take in 1024-element
+ * groups), waves per workgroup (1..16), batch_blocks_per_cu: for the
  * batch kernels the persistent workgroups per CU (1..8), for the plain fills
  * 0 (one workgroup per tile) or the most persistent workgroups per CU (capped
  * by occupancy), and queue_cap: the workgroup's slow-path queue
