@@ -17,7 +17,7 @@ using namespace zg;
 namespace {
 
 const zg_tune DEFAULT_TUNE[ZG_TUNE_CLASSES] = {
-    {2048, 16, 2, 0},   // FILL_F64: persistent, at most 2 workgroups per CU
+    {1024, 16, 2, 0},   // FILL_F64: persistent, at most 2 workgroups per CU
     {4096, 16, 2, 0},   // FILL_F32
     {2048, 8, 0, 0},    // POLAR
     {2048, 16, 2, 0},   // MUTATE
