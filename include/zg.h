@@ -280,7 +280,7 @@ typedef struct zg_server_config {
   uint32_t max_inflight;      /* request slots in flight (admission) */
   uint32_t max_batch;         /* requests per batch launch (<= ZG_MAX_BATCH) */
   uint32_t batch_window_us;   /* how long the batcher waits to fill a batch */
-  uint32_t n_streams;         /* HIP streams with batches in flight (>= 2) */
+  uint32_t n_streams;         /* HIP streams with batches in flight (1 or 2) */
   uint32_t mode;              /* ZG_SERVE_BATCHED or ZG_SERVE_PER_REQUEST */
   uint32_t reserved;
 } zg_server_config;
@@ -312,6 +312,12 @@ typedef struct zg_server_stats {
   double first_arrival_s, last_complete_s;
 } zg_server_stats;
 
+/* Starts a server (batcher and completion threads, its HIP streams, a device
+ * arena of mem_cap_bytes and host-mapped completion records).  ZG_EINVAL for
+ * a zero cap or slot count, max_batch above ZG_MAX_BATCH, n_streams outside
+ * 1..2 or an unknown mode.  Batches on different streams that reserve from
+ * the same handle are ordered by events, so every handle's ranges follow
+ * submission order. */
 zg_status zg_server_create(zg_ctx *ctx, const zg_server_config *cfg, zg_server **out);
 /* Enqueues a request; returns a ticket.  Thread-safe.  ZG_EINVAL for a
  * request larger than the memory cap. */

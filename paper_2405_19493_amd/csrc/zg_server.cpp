@@ -5,7 +5,8 @@
 // slots and output memory (one device arena) are free, gathers what arrived
 // within the batch window (or up to max_batch), and launches the batch as one
 // graph {descriptor upload, counter reservation, persistent batch kernel} on
-// one of n_streams HIP streams in turn, so several batches are in flight.
+// one of n_streams HIP streams (the first idle one, else the next in turn),
+// so several batches are in flight.
 // Every request has a host-mapped completion record that the device writes
 // (the resolved first index, then the completion word, with a system-scope
 // release); a completion thread polls the records of the requests in flight
@@ -113,7 +114,32 @@ struct zg_server {
   HostRec *d_recs = nullptr;    // the same records as the device sees them
   std::vector<int32_t> free_recs;
   std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> stream_idle;   // recorded after each launch on the stream
   uint32_t next_stream = 0;
+  // The stream for the next launch: the first idle one from the round-robin
+  // position (a short request is not queued behind a long one while another
+  // stream has nothing to do), else the round-robin one.
+  uint32_t pick_stream() {
+    const uint32_t n = (uint32_t)streams.size();
+    uint32_t k = next_stream % n;
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint32_t c = (next_stream + j) % n;
+      if (hipEventQuery(stream_idle[c]) == hipSuccess) {
+        k = c;
+        break;
+      }
+    }
+    next_stream = k + 1;
+    return k;
+  }
+  // Per stream handle: the event after the last batch that reserved from it,
+  // and that batch's stream.  A batch on another stream waits for it, so
+  // that reservations of one handle happen in submission order.
+  struct LastUse {
+    hipEvent_t ev = nullptr;
+    uint32_t si = 0;
+  };
+  std::vector<LastUse> last_use;
   std::chrono::steady_clock::time_point t0;
 
   std::mutex mu;
@@ -246,16 +272,26 @@ void zg_server::batch_loop() {
     std::vector<zg_status> sts(groups, ZG_OK);
     for (size_t g2 = 0; g2 < groups; ++g2) {
       const size_t k0 = g2 * per, k1 = g2 + 1 == groups ? batch.size() : k0 + per;
-      hipStream_t stream = streams[next_stream++ % streams.size()];
+      const uint32_t si = pick_stream();
+      hipStream_t stream = streams[si];
       BatchPlan plan;
       zg_status st = plan_batch(ctx, reqs.data() + k0, (uint32_t)(k1 - k0), flags.data() + k0, 1u,
                                 &plan, firsts.data() + k0);
       BatchSlot *slot = nullptr;
       if (st == ZG_OK) st = acquire_slot(ctx, &slot);
       if (st == ZG_OK) {
-        st = slot->launch(ctx, plan, stream, /*full=*/true, nullptr);
+        // earlier batches on other streams that reserve from the same handles
+        for (size_t k = k0; k < k1 && st == ZG_OK; ++k) {
+          const LastUse &u = last_use[reqs[k].handle];
+          if (u.ev && u.si != si && hipStreamWaitEvent(stream, u.ev, 0) != hipSuccess)
+            st = hip_fail(ctx, hipGetLastError(), "handle order");
+        }
+        if (st == ZG_OK) st = slot->launch(ctx, plan, stream, /*full=*/true, nullptr);
+        if (st == ZG_OK)
+          for (size_t k = k0; k < k1; ++k) last_use[reqs[k].handle] = LastUse{slot->done, si};
         release_slot(ctx, slot);
       }
+      if (st == ZG_OK) (void)hipEventRecord(stream_idle[si], stream);
       sts[g2] = st;
     }
     lk.lock();
@@ -315,7 +351,7 @@ zg_status zg_server_create(zg_ctx *ctx, const zg_server_config *cfg, zg_server *
   if (!ctx || !cfg || !out) return ZG_EINVAL;
   if (cfg->mem_cap_bytes < ARENA_ALIGN || cfg->max_inflight == 0 || cfg->max_inflight > 1u << 20 ||
       cfg->max_batch == 0 || cfg->max_batch > ZG_MAX_BATCH || cfg->n_streams < 1 ||
-      cfg->n_streams > 16 || cfg->mode > ZG_SERVE_PER_REQUEST)
+      cfg->n_streams > 2 || cfg->mode > ZG_SERVE_PER_REQUEST)
     return ZG_EINVAL;
   DeviceGuard g(ctx->device);
   zg_server *s = new zg_server();
@@ -332,9 +368,13 @@ zg_status zg_server_create(zg_ctx *ctx, const zg_server_config *cfg, zg_server *
     hipStream_t st = nullptr;
     e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e == hipSuccess) s->streams.push_back(st);
+    hipEvent_t ev = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) s->stream_idle.push_back(ev);
   }
   if (e != hipSuccess) {
     zg_status st = hip_fail(ctx, e, "server create");
+    for (hipEvent_t ev : s->stream_idle) (void)hipEventDestroy(ev);
     for (hipStream_t st2 : s->streams) (void)hipStreamDestroy(st2);
     if (s->recs) (void)hipHostFree(s->recs);
     if (s->arena_base) (void)hipFree(s->arena_base);
@@ -345,6 +385,7 @@ zg_status zg_server_create(zg_ctx *ctx, const zg_server_config *cfg, zg_server *
   s->owner.reset(new std::atomic<uint64_t>[cfg->max_inflight]);
   for (uint32_t k = 0; k < cfg->max_inflight; ++k) s->owner[k].store(0);
   s->active_pos.assign(cfg->max_inflight, 0);
+  s->last_use.assign(ZG_MAX_HANDLES, zg_server::LastUse{});
   s->active.reserve(cfg->max_inflight);
   s->arena.init(s->cfg.mem_cap_bytes);
   for (int32_t k = (int32_t)cfg->max_inflight - 1; k >= 0; --k) s->free_recs.push_back(k);
@@ -515,6 +556,7 @@ zg_status zg_server_destroy(zg_server *s) {
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
   }
+  for (hipEvent_t ev : s->stream_idle) (void)hipEventDestroy(ev);
   if (s->recs) (void)hipHostFree(s->recs);
   if (s->arena_base) (void)hipFree(s->arena_base);
   delete s;

@@ -36,10 +36,11 @@ def make_trace(rate, duration_s, n_handles, seed=5, min_n=16, max_n=1 << 24):
     return t, sizes, dtypes, handles
 
 
-def run_mode(ctx, mode, trace, handles, mem_cap, sample, sample_n_max, seed_base, window_us):
+def run_mode(ctx, mode, trace, handles, mem_cap, sample, sample_n_max, seed_base, window_us,
+             n_streams=2):
     t_arr, sizes, dtypes, hidx = trace
     srv = Z.Server(ctx, mem_cap_bytes=mem_cap, max_inflight=8192, max_batch=4096,
-                   batch_window_us=window_us, n_streams=2, mode=mode)
+                   batch_window_us=window_us, n_streams=n_streams, mode=mode)
     tickets = [None] * len(t_arr)
     keep = {}
     done_evt = threading.Event()
@@ -110,11 +111,11 @@ def alone_vs_mix(ctx, keep, trace, seed_of_handle, stream_of_handle):
     return bad
 
 
-def replay_mode(ctx, mode, trace, handles, mem_cap, window_us):
+def replay_mode(ctx, mode, trace, handles, mem_cap, window_us, n_streams=2):
     """C-driven open-loop replay of the trace; returns the server's figures."""
     t_arr, sizes, dtypes, hidx = trace
     srv = Z.Server(ctx, mem_cap_bytes=mem_cap, max_inflight=8192, max_batch=4096,
-                   batch_window_us=window_us, n_streams=2, mode=mode)
+                   batch_window_us=window_us, n_streams=n_streams, mode=mode)
     hs = np.asarray(handles, dtype=np.int64)[hidx]
     t0 = time.perf_counter()
     srv.replay(hs, sizes, dtypes, t_arr, timeout_s=600.0)

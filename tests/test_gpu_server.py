@@ -158,3 +158,49 @@ def test_server_replay_matches_counters(ctx, zg):
         srv.close()
         for x in h:
             ctx.zg_stream_close(x)
+
+
+def test_server_handle_order_across_streams(ctx, zg):
+    """Many small batches on both streams, three handles: every request's
+    range follows its handle's submission order exactly (batches on different
+    streams that reserve from one handle are ordered), and the output is the
+    request run alone at that range."""
+    seeds = [300, 301, 302]
+    handles = [ctx.zg_stream_open(seeds[h], 40 + h, zg.ZG_SPLITMIX64) for h in range(3)]
+    rng = np.random.Generator(np.random.PCG64(77))
+    m = 400
+    sizes = np.exp(rng.uniform(np.log(16), np.log(2 ** 18), m)).astype(np.int64)
+    hidx = rng.integers(0, 3, m)
+    srv = zg.Server(ctx, mem_cap_bytes=256 << 20, max_inflight=256, max_batch=6,
+                    batch_window_us=0, n_streams=2, mode=0)
+    try:
+        tickets = [srv.submit(handles[int(h)], int(n)) for n, h in zip(sizes, hidx)]
+        running = [0, 0, 0]
+        for k, t in enumerate(tickets):
+            c = srv.wait(t, 60.0)
+            h = int(hidx[k])
+            assert c["status"] == zg.ZG_OK and c["first_index"] == running[h], (k, c["first_index"], running[h])
+            running[h] += int(sizes[k])
+            if k % 40 == 0:
+                got = srv.output(c, int(sizes[k]), zg.ZG_F64).clone()
+                alone = torch.empty_like(got)
+                ctx.zg_fill(alone, kind=zg.ZG_SPLITMIX64, seed=seeds[h], stream=40 + h,
+                            first_index=c["first_index"])
+                torch.cuda.synchronize()
+                assert torch.equal(alone.view(torch.uint8), got.view(torch.uint8)), k
+            srv.release(t)
+        srv.drain()
+        assert srv.stats()["batches"] > 1
+        for h in range(3):
+            assert ctx.zg_stream_get_counter(handles[h]) == running[h]
+    finally:
+        srv.close()
+        for x in handles:
+            ctx.zg_stream_close(x)
+
+
+def test_server_rejects_more_than_two_streams(ctx, zg):
+    with pytest.raises(zg.ZgError) as e:
+        zg.Server(ctx, mem_cap_bytes=1 << 20, max_inflight=4, max_batch=4, batch_window_us=0,
+                  n_streams=3, mode=0)
+    assert e.value.status == zg.ZG_EINVAL
