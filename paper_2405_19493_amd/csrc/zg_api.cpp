@@ -153,6 +153,7 @@ zg_status zg_create(int hip_device, zg_ctx **out) {
   }
   h->r = ctx->table.r;
   build_lcg_tables(&h->lcg);
+  build_log_tables(&h->logt);
   hipError_t e = hipMalloc(&ctx->d_tables, sizeof(DevTables));
   if (e == hipSuccess) e = hipMemcpy(ctx->d_tables, h, sizeof(DevTables), hipMemcpyHostToDevice);
   delete h;

@@ -36,6 +36,21 @@ struct Fast32 {
 };
 
 // Everything the kernels read, in one device allocation per context.
+// Logarithm table of the polar method: for m in [sqrt(1/2), sqrt(2)) split
+// at the top 7 mantissa bits of its binade (index LOG_I0 + k), invc[k] is a
+// 7-bit approximation of 1/m (exactly 1 next to m = 1), so that m invc - 1 is
+// exact, and -log(invc) = hi + lo with hi a multiple of 2^-33.
+constexpr int LOG_N = 129;
+constexpr int LOG_I0 = 53;
+struct LogEnt {
+  double invc;
+  double hi;
+};
+struct LogTables {
+  LogEnt e[LOG_N];
+  double lo[LOG_N];
+};
+
 struct DevTables {
   Fast64 fast64[ZG_LAYERS];
   Fast32 fast32[ZG_LAYERS];
@@ -46,6 +61,7 @@ struct DevTables {
   double r;
   double pad[7];
   LcgTables lcg;
+  LogTables logt;
 };
 
 // Operation selector shared by the plain and batch kernels.
@@ -126,6 +142,7 @@ size_t batch_class_lds_bytes(int cls, uint32_t waves);
 
 zg_status build_table(zg_table_view *t);
 void build_lcg_tables(LcgTables *L);
+void build_log_tables(LogTables *L);
 Affine lcg_power(uint64_t k);
 
 }  // namespace zg

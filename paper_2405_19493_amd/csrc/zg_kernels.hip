@@ -125,65 +125,66 @@ DEV double sym53(uint64_t W) {
   return fma((double)hi, 0x1p-20, fma((double)lo, 0x1p-52, -1.0));
 }
 
-// Natural logarithm of x in [2^-1022, 1) (the polar method's s), from the
-// binary exponent and the series log((1 + t)/(1 - t)) = 2 atanh t:
-// x = 2^e m with m in [sqrt(1/2), sqrt(2)), f = m - 1, t = f / (2 + f),
-// log m = f - h + t (h + R), h = f^2 / 2, R = sum_{k=1..10} 2 t^2k / (2k + 1).
-// |t| <= 0.1716, so the first omitted term is below 2^-53 of the sum.  The
-// large terms are summed with their rounding errors carried: h as h + hl
-// (exact), f - h and e ln2_hi + (f - h) by error-free two-sums; ln 2 is split
-// so that e ln2_hi is exact (32 significant bits).  Within 0.67 ulp of the
-// true logarithm on (0, 1) (checked against an extended-precision logarithm
-// on 3e7 points).
-DEV double log_unit(double x) {
+// Natural logarithm of x in [2^-1022, 1) (the polar method's s):
+// x = 2^e m with m in [sqrt(1/2), sqrt(2)); the table entry of m's interval
+// gives invc ~ 1/c and -log(invc) = hi + lo, so that
+// log x = e ln2 + (hi + lo) + log(1 + r), r = m invc - 1 (exact: invc has 7
+// significant bits), |r| < 2^-6.7, and log(1 + r) = r + r^2 Q(r) with
+// Q = sum_{k=2..9} (-1)^(k+1) r^(k-2) / k (the first omitted term is below
+// 2^-60 of r).  e ln2_hi + hi is exact (both are multiples of 2^-33); r is
+// added to it by an error-free two-sum, and the small terms last.  Within
+// 0.51 ulp of the true logarithm on (0, 1) (checked against an
+// extended-precision logarithm on 3e7 points).
+DEV double log_unit(double x, const LogTables &L) {
   int e;
   double m = frexp(x, &e);   // m in [1/2, 1)
   if (m < 0x1.6a09e667f3bcdp-1) {
     m *= 2.0;
     --e;
   }
-  const double f = m - 1.0;
-  const double t = f / (2.0 + f);
-  const double z = t * t;
-  double R = 2.0 / 21.0;
-  R = fma(R, z, 2.0 / 19.0);
-  R = fma(R, z, 2.0 / 17.0);
-  R = fma(R, z, 2.0 / 15.0);
-  R = fma(R, z, 2.0 / 13.0);
-  R = fma(R, z, 2.0 / 11.0);
-  R = fma(R, z, 2.0 / 9.0);
-  R = fma(R, z, 2.0 / 7.0);
-  R = fma(R, z, 2.0 / 5.0);
-  R = fma(R, z, 2.0 / 3.0);
-  R = R * z;
-  const double hf = 0.5 * f;
-  const double h = hf * f;
-  const double hl = fma(hf, f, -h);   // h + hl = f^2 / 2 exactly
-  const double a = f - h;             // |h| <= 0.15 |f|: a + ae = f - h exactly
-  const double ae = (f - a) - h;
+  const int k = (int)((__double2hiint(m) >> 13) & 0xFF) - LOG_I0;   // low exponent bit, top 7 mantissa bits
+  const LogEnt t = L.e[k];
+  const double r = fma(m, t.invc, -1.0);
+  double Q = 1.0 / 9.0;
+  Q = fma(Q, r, -1.0 / 8.0);
+  Q = fma(Q, r, 1.0 / 7.0);
+  Q = fma(Q, r, -1.0 / 6.0);
+  Q = fma(Q, r, 1.0 / 5.0);
+  Q = fma(Q, r, -1.0 / 4.0);
+  Q = fma(Q, r, 1.0 / 3.0);
+  Q = fma(Q, r, -0.5);
   const double de = (double)e;
-  const double big = de * 0x1.62e42ffp-1;   // e ln2_hi, exact
-  const double small = ((t * (h + R) - hl) + ae) + de * -0x1.718432a1b0e26p-35;   // e ln2_lo
-  const double r1 = big + a;
-  const double r1e = e != 0 ? (big - r1) + a : (a - r1) + big;   // the larger term first
-  return r1 + (r1e + small);
+  const double big = fma(de, 0x1.62e42ffp-1, t.hi);   // e ln2_hi + hi, exact
+  const double s1 = big + r;
+  const double bb = s1 - big;
+  const double err = (big - (s1 - bb)) + (r - bb);    // s1 + err = big + r
+  const double small = fma(r * r, Q, err) + fma(de, -0x1.718432a1b0e26p-35, L.lo[k]);   // e ln2_lo
+  return s1 + small;
+}
+
+// The log table of the polar kernels in LDS (whole block; then a barrier).
+DEV void load_log_table(const DevTables *T, LogTables &L) {
+  const double *src = (const double *)&T->logt;
+  double *dst = (double *)&L;
+  for (uint32_t i = threadIdx.x; i < sizeof(LogTables) / sizeof(double); i += blockDim.x)
+    dst[i] = src[i];
 }
 
 // Polar attempt from the words of draws d and d+1 (Knuth; Random.nextGaussian).
-DEV PolarStep polar_from_words(uint64_t W1, uint64_t W2, uint32_t d) {
+DEV PolarStep polar_from_words(uint64_t W1, uint64_t W2, uint32_t d, const LogTables &L) {
   const double v1 = sym53(W1);
   const double v2 = sym53(W2);
   const double ss = v1 * v1 + v2 * v2;
   if (ss >= 1.0 || ss == 0.0) return {0, 0.0, 0.0, d + 2};
-  const double m = sqrt(-2.0 * log_unit(ss) / ss);
+  const double m = sqrt(-2.0 * log_unit(ss, L) / ss);
   return {1, v1 * m, v2 * m, d};
 }
 
 template <int KIND>
-DEV PolarStep polar_attempt(const DevTables *T, uint64_t seed, uint32_t s, uint64_t p, uint32_t d,
-                            uint32_t dmax) {
+DEV PolarStep polar_attempt(const DevTables *T, const LogTables &L, uint64_t seed, uint32_t s,
+                            uint64_t p, uint32_t d, uint32_t dmax) {
   if (d + 1 >= dmax) return {-1, 0.0, 0.0, d};
-  return polar_from_words(wordk<KIND>(T, seed, s, p, d), wordk<KIND>(T, seed, s, p, d + 1), d);
+  return polar_from_words(wordk<KIND>(T, seed, s, p, d), wordk<KIND>(T, seed, s, p, d + 1), d, L);
 }
 
 // --------------------------------------------------------- wave utilities
@@ -258,11 +259,15 @@ DEV double flip_hi(double x, uint32_t whi) {
 // elements whose pair straddles a stream boundary or the tile edge.  The
 // queue is drained 64 entries per round, one attempt per lane per round.
 
+// LDS bytes of the log table at the start of a polar kernel's LDS.
+constexpr size_t POLAR_LOG_BYTES = (sizeof(LogTables) + 15) / 16 * 16;
+
 // Context of the polar path.
 struct PolarCtx {
   const DevTables *T;
   uint32_t dmax;
   uint32_t *flags;
+  const LogTables *L;   // in LDS
 };
 
 struct Queue {
@@ -296,7 +301,7 @@ DEV void drain_polar(const Job &J, const PolarCtx &C, Queue &Q, uint32_t keep, u
       uint32_t s;
       uint64_t v;
       split(J, e, s, v);
-      PolarStep st = polar_attempt<KIND>(C.T, J.seed, s, v >> 1, d, C.dmax);
+      PolarStep st = polar_attempt<KIND>(C.T, *C.L, J.seed, s, v >> 1, d, C.dmax);
       if (st.status == 0) {
         pend = true;
         requeue = qent(off, st.next_d, fl);
@@ -396,7 +401,7 @@ DEV void polar_step(const Job &J, const PolarCtx &C, const LaneConst &LC, Queue 
       W1 = mix64(z);
       W2 = mix64(z + (GAMMA << 40));
     }
-    const PolarStep st = polar_from_words(W1, W2, 0);
+    const PolarStep st = polar_from_words(W1, W2, 0, *C.L);
     const bool acc = st.status == 1 && C.dmax >= 2;
     *(double2 *)((double *)J.out + e0) = make_double2(st.z1, st.z2);   // placeholder if rejected
     push_a = !acc;
@@ -1045,11 +1050,15 @@ template <int KIND>
 __global__ __launch_bounds__(1024) void k_polar(Job J, const DevTables *__restrict__ T,
                                                 uint32_t dmax, uint32_t *flags, uint32_t tile,
                                                 uint32_t head) {
-  extern __shared__ uint32_t s_q[];   // waves x QCAP
+  extern __shared__ __align__(16) unsigned char s_polar[];   // log table, then waves x QCAP
+  LogTables &Lt = *(LogTables *)s_polar;
+  uint32_t *s_q = (uint32_t *)(s_polar + POLAR_LOG_BYTES);
+  load_log_table(T, Lt);
+  __syncthreads();
   const uint32_t wave = uni(threadIdx.x >> 6);
   const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   const uint64_t b = head + gw * tile;
-  const PolarCtx C{T, dmax, flags};
+  const PolarCtx C{T, dmax, flags, &Lt};
   if (b < J.n_total || (gw == 0 && head)) {
     const LaneConst LC = lane_constants<OP_POLAR, KIND>(T);
     const uint64_t e_end = b + tile < J.n_total ? b + tile : J.n_total;
@@ -1185,12 +1194,16 @@ __global__ __launch_bounds__(1024) void k_bpolar(DevRequest *R, const BatchHeade
   constexpr int C = batch_class(OP_POLAR, KIND);
   const uint32_t cnt = H->cls_cnt[C];
   if (blockIdx.x >= cnt) return;
-  extern __shared__ uint32_t s_q[];   // waves x QCAP
+  extern __shared__ __align__(16) unsigned char s_polar[];   // log table, then waves x QCAP
+  LogTables &Lt = *(LogTables *)s_polar;
+  uint32_t *s_q = (uint32_t *)(s_polar + POLAR_LOG_BYTES);
+  load_log_table(T, Lt);
+  __syncthreads();
   const uint64_t *items = (const uint64_t *)((const char *)H + H->items_off);
   const uint32_t off = H->cls_off[C];
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wave = uni(threadIdx.x >> 6);
-  const PolarCtx Cx{T, H->dmax, flags};
+  const PolarCtx Cx{T, H->dmax, flags, &Lt};
   const LaneConst LC = lane_constants<OP_POLAR, KIND>(T);
   for (uint32_t k = blockIdx.x; k < cnt; k += gridDim.x) {
     const uint64_t it = items[off + k];
@@ -1248,7 +1261,8 @@ static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax
     if (tiles == 0) tiles = 1;   // head-only jobs still need wave 0
     uint64_t blocks = (tiles + waves - 1) / waves;
     hipLaunchKernelGGL((k_polar<KIND>), dim3((uint32_t)blocks), dim3(64 * waves),
-                       (size_t)waves * QCAP * sizeof(uint32_t), stream, J, T, dmax, flags, tile,
+                       POLAR_LOG_BYTES + (size_t)waves * QCAP * sizeof(uint32_t), stream, J, T, dmax,
+                       flags, tile,
                        head);
   }
   return hipGetLastError();
@@ -1314,7 +1328,9 @@ const void *kernel_batch_class(int cls) {
 }
 
 size_t batch_class_lds_bytes(int cls, uint32_t waves) {
-  return cls >= batch_class(OP_POLAR, ZG_SPLITMIX64) ? (size_t)waves * QCAP * sizeof(uint32_t) : 0;
+  return cls >= batch_class(OP_POLAR, ZG_SPLITMIX64)
+             ? POLAR_LOG_BYTES + (size_t)waves * QCAP * sizeof(uint32_t)
+             : 0;
 }
 
 }  // namespace zg

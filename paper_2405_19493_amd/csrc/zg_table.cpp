@@ -218,6 +218,32 @@ Affine lcg_power(uint64_t k) {
   return result;
 }
 
+void build_log_tables(LogTables *L) {
+  for (int k = 0; k < LOG_N; ++k) {
+    const int idx = k + LOG_I0;
+    // the interval of m: the lower binade [1/2, 1) in steps of 2^-8, the
+    // upper [1, 2) in steps of 2^-7
+    long double lo, hi;
+    if (idx < 128) {
+      lo = 0.5L * (1 + idx / 128.0L);
+      hi = 0.5L * (1 + (idx + 1) / 128.0L);
+    } else {
+      lo = 1 + (idx - 128) / 128.0L;
+      hi = 1 + (idx - 127) / 128.0L;
+    }
+    long double ic = 1.0L;
+    if (idx != 127 && idx != 128) {   // next to m = 1 the reduction is m - 1 itself
+      int ex = 0;
+      const long double f = std::frexp(1.0L / (0.5L * (lo + hi)), &ex);
+      ic = std::ldexp(std::rint(std::ldexp(f, 7)), ex - 7);   // 7 significant bits
+    }
+    const long double lc = -std::log(ic);
+    const double h = (double)(std::rint(std::ldexp(lc, 33)) / 8589934592.0L);
+    L->e[k] = {(double)ic, h};
+    L->lo[k] = (double)(lc - (long double)h);
+  }
+}
+
 void build_lcg_tables(LcgTables *L) {
   // jump[b][x] = x * 256^b steps, built by repeated composition
   for (int b = 0; b < LCG_JUMP_BYTES; ++b) {
