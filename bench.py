@@ -78,6 +78,18 @@ def time_kernel(fn, steps, warmup, torch):
     return sum(ms) / len(ms), ms, wall
 
 
+def median_ci(xs, z=3.29):
+    """Median of the per-launch times and a distribution-free 99.9% confidence
+    interval for it (order statistics at n/2 -+ z sqrt(n)/2)."""
+    v = sorted(xs)
+    n = len(v)
+    med = v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+    half = z * (n ** 0.5) / 2.0
+    lo = max(0, int(n / 2.0 - half))
+    hi = min(n - 1, int(n / 2.0 + half + 0.999))
+    return med, [v[lo], v[hi]]
+
+
 def cpu_baseline(seconds):
     """The oracle (oracle/zg_oracle.c) on a bounded sample of the same workload:
     whole streams of 4096 variates, seed 7, SplitMix64, one stream per call, the
@@ -277,6 +289,7 @@ def main():
     main_key = "zig" if "zig" in res else "polar"
     ms, all_ms, wall = res[main_key]
     wall_ms = wall * 1e3 / args.steps
+    med, ci = median_ci(all_ms)
     bytes_per = 8.0 * n
     achieved = bytes_per / (ms * 1e-3) / 1e9
     kernel = "k_zig<OP_ZIG64>" if main_key == "zig" else "k_polar"
@@ -290,6 +303,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": wall_ms,
         "kernel_ms": ms,
+        "kernel_ms_median": med,
+        "kernel_ms_median_ci999": ci,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
