@@ -470,8 +470,10 @@ DEV void polar_tile(const Job &J, const PolarCtx &C, const LaneConst &LC, uint32
 // next attempt, and storing the value when that decides it.  The 3-4% left
 // undecided, and the base-strip attempts (the tail, with its logarithm), go
 // to a retry queue that later rounds finish with the whole attempt loop:
-// whole rounds of 64 at the start of the next tile of the same job, the
-// rest at the end.  Pooling keeps the drain rounds nearly full: a tile of
+// whole rounds of 64 at the start of the workgroup's next tile, the rest at
+// the end of the kernel (the batch kernels, whose consecutive tiles belong to
+// different jobs, finish them with each tile).  Pooling keeps the drain
+// rounds nearly full: a tile of
 // 16 x 2048 elements has about 900 slow elements, one wave's share about 57.
 //
 // Queue overflow (more slow elements than the queue holds, which hash words
