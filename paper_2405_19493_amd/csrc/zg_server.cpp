@@ -28,6 +28,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "zg_arena.h"
 #include "zg_ctx.h"
 
 using namespace zg;
@@ -37,44 +38,6 @@ namespace {
 constexpr uint64_t ARENA_ALIGN = 256;
 // at most this many requests admitted together are launched one by one
 constexpr size_t SOLO_MAX = 4;
-
-// First-fit allocator over [0, size) with coalescing of free neighbours.
-class Arena {
- public:
-  void init(uint64_t size) {
-    free_.clear();
-    if (size) free_[0] = size;
-  }
-  bool alloc(uint64_t bytes, uint64_t *off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < bytes) continue;
-      *off = it->first;
-      const uint64_t rest = it->second - bytes, start = it->first + bytes;
-      free_.erase(it);
-      if (rest) free_[start] = rest;
-      return true;
-    }
-    return false;
-  }
-  void release(uint64_t off, uint64_t bytes) {
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<uint64_t, uint64_t> free_;
-};
 
 // Completion record in host memory, written by the device.
 struct HostRec {
