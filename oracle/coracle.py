@@ -95,6 +95,8 @@ def lib():
         L.orc_mutate.restype = u64
         L.orc_words.argtypes = [i32, u64, u32, u32, u64, u64, vp]
         L.orc_words.restype = None
+        L.orc_seq_f64.argtypes = [vp, i32, u64, u32, u64, u64, vp, u64, vp, vp, vp, vp]
+        L.orc_seq_f64.restype = u64
         _lib = L
     return _lib
 
@@ -214,3 +216,24 @@ def polar_core(u1, u2):
     o2 = ctypes.c_double()
     ok = lib().orc_polar_core(u1, u2, ctypes.byref(o1), ctypes.byref(o2))
     return bool(ok), o1.value, o2.value
+
+
+def seq_f64(kind, seed, s, first, n, words=None, limit=None):
+    """Sequential consumption: n variates taken from one generator in order
+    (stream s of (seed, kind) from word position `first`, or, with kind 0,
+    the crafted uint64 array `words`).  Returns (values, outcome codes, each
+    variate's first position, the position after the last word read, the
+    number of variates the generator could not complete)."""
+    out = np.empty(n, dtype=np.float64)
+    cls = np.empty(n, dtype=np.uint8)
+    starts = np.empty(n, dtype=np.uint64)
+    nxt = ctypes.c_uint64()
+    arr = None
+    if kind == 0:
+        arr = np.ascontiguousarray(words, dtype=np.uint64)
+        lim = arr.size if limit is None else limit
+    else:
+        lim = (2**64 - 1) if limit is None else limit
+    fails = lib().orc_seq_f64(ctypes.byref(table()), kind, seed & (2**64 - 1), s, first, n,
+                              _p(arr), lim, _p(out), _p(cls), _p(starts), ctypes.byref(nxt))
+    return out, cls, starts, int(nxt.value), int(fails)

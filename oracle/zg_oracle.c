@@ -447,3 +447,97 @@ void orc_words(int kind, uint64_t seed, uint32_t s, uint32_t d, uint64_t first, 
                uint64_t *out) {
   for (uint64_t k = 0; k < n; ++k) out[k] = orc_word(kind, seed, s, first + k, d);
 }
+
+/* ------------------------------------------------- sequential consumption */
+
+/* The paper's nextGaussian(random) (Section 2, Listing 2) takes its uniforms
+ * from one generator object, in call order.  Here that generator is stream s
+ * of (seed, kind) read from position `first`: its word at position p is
+ * W(seed, s, p, 0), which for stream 0 is SplittableRandom(seed).nextLong()
+ * number p (SplitMix64) or the numerator of Random(seed).nextDouble() number p
+ * shifted left by 11 (LCG).  kind 0 reads a caller-given list instead, word p
+ * being list[p], for crafted streams.  Positions >= limit are unavailable. */
+typedef struct {
+  int kind;
+  uint64_t seed;
+  uint32_t s;
+  const uint64_t *list;
+  uint64_t limit;
+  uint64_t pos;
+} orc_gen;
+
+static int gen_next(orc_gen *g, uint64_t *W) {
+  if (g->pos >= g->limit) return 0;
+  *W = g->kind == 0 ? g->list[g->pos] : orc_word(g->kind, g->seed, g->s, g->pos, 0);
+  g->pos++;
+  return 1;
+}
+
+/* One FP64 variate taken from the generator: each attempt reads one word;
+ * a wedge test reads one more (U), the base strip two more (U1+, then U2);
+ * after a rejection the next attempt reads the next unread word.  The
+ * arithmetic of each attempt is that of orc_zig_f64.  Returns 0 (value NaN)
+ * when the generator runs out first. */
+static int seq_variate(const orc_table *T, orc_gen *g, double *out, uint8_t *cls) {
+  for (int att = 1;; ++att) {
+    uint64_t W, W1, W2;
+    if (!gen_next(g, &W)) {
+      *cls = outcome(3, att);
+      break;
+    }
+    int i = (int)(W >> 57);
+    int neg = (int)((W >> 56) & 1);
+    uint64_t j = (W >> 3) & ((1ULL << 53) - 1);
+    double x = (double)j * T->w53[i];
+    if (j < T->k53[i]) {
+      *cls = outcome(0, att);
+      *out = neg ? -x : x;
+      return 1;
+    }
+    if (i == 0) {
+      if (!gen_next(g, &W1) || !gen_next(g, &W2)) {
+        *cls = outcome(3, att);
+        break;
+      }
+      double a = -log(u53p(W1)) / T->r;
+      if (u53(W2) < exp(-0.5 * (a * a))) {
+        double xt = T->r + a;
+        *cls = outcome(2, att);
+        *out = neg ? -xt : xt;
+        return 1;
+      }
+    } else {
+      if (!gen_next(g, &W1)) {
+        *cls = outcome(3, att);
+        break;
+      }
+      double y = T->y[i - 1] + u53(W1) * T->dy[i];
+      if (y < exp(-0.5 * (x * x))) {
+        *cls = outcome(1, att);
+        *out = neg ? -x : x;
+        return 1;
+      }
+    }
+  }
+  *out = nan64();
+  return 0;
+}
+
+/* n variates of sequential consumption starting at position `first`.
+ * starts (optional) receives each variate's first position; *next the
+ * position after the last word read.  Returns the number of variates the
+ * generator could not complete (each NaN). */
+uint64_t orc_seq_f64(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t first,
+                     uint64_t n, const uint64_t *list, uint64_t limit, double *out,
+                     uint8_t *cls, uint64_t *starts, uint64_t *next) {
+  orc_gen g = {kind, seed, s, list, limit, first};
+  uint64_t fails = 0;
+  for (uint64_t k = 0; k < n; ++k) {
+    uint8_t c = 0;
+    if (starts) starts[k] = g.pos;
+    if (!seq_variate(T, &g, &out[k], &c)) fails++;
+    if (cls) cls[k] = c;
+  }
+  *next = g.pos;
+  return fails;
+}
