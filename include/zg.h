@@ -167,6 +167,37 @@ zg_status zg_uniform_words(zg_ctx *ctx, uint64_t *d_out, uint64_t n, zg_kind kin
 zg_status zg_mutate(zg_ctx *ctx, double *d_x, uint64_t n, double sigma, zg_kind kind,
                     uint64_t seed, uint32_t stream, uint64_t first_index, void *hip_stream);
 
+/* Sequential consumption (Section 2, Listing 2: nextGaussian(random) takes
+ * its uniforms from one generator object, in call order): d_out[k] is the
+ * k-th of n successive FP64 ziggurat variates that all read one generator in
+ * order.  The generator is stream `stream` of (seed, kind) from word position
+ * first_word; its word at position p is W(seed, stream, p, 0), so stream 0 is
+ * SplittableRandom(seed).nextLong() (ZG_SPLITMIX64) or the numerators of
+ * Random(seed).nextDouble() (ZG_JAVA_LCG48) in call order.  An attempt reads
+ * one word, a wedge test one more, the base strip two more; after a rejection
+ * the next attempt reads the next unread word.  Each attempt's arithmetic is
+ * zg_fill's, with no draw budget.
+ * d_next_word (device, 8-byte aligned, or NULL) receives the position after
+ * the last word read: passed back as first_word it continues the generator.
+ * d_work: device workspace of work_bytes >= zg_sequential_workspace(n) bytes,
+ * owned by the caller and in use until the call's work on hip_stream has
+ * completed (the library allocates nothing here).
+ * d_out: n doubles, 8-byte aligned.  n = 0 does nothing.  Asynchronous.
+ * n is limited to ZG_SEQ_MAX_N, the largest size checked on the device so far.
+ * Errors: ZG_EINVAL (null, enum, alignment, stream limit, n > ZG_SEQ_MAX_N,
+ * no or too small workspace), ZG_ERANGE (the scanned positions, about 1.05 n + 16 sqrt(n) from
+ * first_word, would pass the stream's window: ZG_SM64_WINDOW or
+ * ZG_LCG_WINDOW words), ZG_ENOMEM, ZG_EHIP.  Should the variates need words
+ * past the window after all, the rest are NaN and ZG_FLAG_RANGE is raised. */
+zg_status zg_fill_sequential(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kind, uint64_t seed,
+                             uint32_t stream, uint64_t first_word, uint64_t *d_next_word,
+                             void *d_work, uint64_t work_bytes, void *hip_stream);
+
+#define ZG_SEQ_MAX_N 1000000ull
+
+/* Workspace bytes zg_fill_sequential needs for n variates (0 for n = 0). */
+zg_status zg_sequential_workspace(uint64_t n, uint64_t *bytes);
+
 /* Test hook: one ziggurat attempt per crafted word.  d_class[i] = 0 (fast),
  * 1 (wedge), 2 (tail); d_x[i] = the signed first-word candidate
  * (double)j * w53[i].  All pointers are device memory. */
@@ -178,8 +209,12 @@ zg_status zg_decide_words(zg_ctx *ctx, const uint64_t *d_words, uint64_t n, uint
 zg_status zg_error_flags(zg_ctx *ctx, uint32_t *flags, int clear);
 
 /* Test knobs.  ZG_KNOB_DMAX: draw budget (1..256, default 256), so that a
- * test can force budget exhaustion from the host. */
+ * test can force budget exhaustion from the host.  ZG_KNOB_SEQ_SPANS: caps
+ * the positions the parallel pass of zg_fill_sequential scans at value x
+ * 16384 (0 = automatic, the default), so that a test can make its
+ * one-lane finish produce the rest. */
 #define ZG_KNOB_DMAX 1
+#define ZG_KNOB_SEQ_SPANS 2
 zg_status zg_set_test_knob(zg_ctx *ctx, int knob, int64_t value);
 
 /* ------------------------------------------------ device-resident counters */

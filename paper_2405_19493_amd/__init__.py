@@ -35,6 +35,8 @@ ZG_F32 = 1
 ZG_FLAG_BUDGET = 1
 ZG_FLAG_RANGE = 2
 ZG_KNOB_DMAX = 1
+ZG_KNOB_SEQ_SPANS = 2
+ZG_SEQ_MAX_N = 1000000
 ZG_OP_FILL = 0
 ZG_OP_MUTATE = 1
 ZG_NO_HANDLE = -1
@@ -134,6 +136,8 @@ def _load():
         "zg_fill": [P, P, U64, ctypes.c_int, ctypes.c_int, ctypes.c_int, U64, U32, U64, P],
         "zg_fill_streams": [P, P, U64, U32, ctypes.c_int, ctypes.c_int, ctypes.c_int, U64, U32, U64, P],
         "zg_uniform_words": [P, P, U64, ctypes.c_int, U64, U32, U32, U64, P],
+        "zg_fill_sequential": [P, P, U64, ctypes.c_int, U64, U32, U64, P, P, U64, P],
+        "zg_sequential_workspace": [U64, P],
         "zg_mutate": [P, P, U64, D, ctypes.c_int, U64, U32, U64, P],
         "zg_decide_words": [P, P, U64, P, P, P],
         "zg_error_flags": [P, P, ctypes.c_int],
@@ -278,6 +282,25 @@ class Context:
         self._c(lib.zg_uniform_words(self.h, _ptr(out), out.numel(), kind, seed & (2**64 - 1),
                                      stream, draw, first_index, _stream(hip_stream)),
                 "zg_uniform_words")
+        return out
+
+    def zg_fill_sequential(self, out, kind=ZG_SPLITMIX64, seed=0, stream=0, first_word=0,
+                           next_word=None, work=None, hip_stream=None):
+        """out (float64) <- successive variates reading one generator in order
+        from word position first_word; next_word: optional 1-element int64
+        device tensor receiving the position after the last word read; work:
+        optional uint8 device tensor of zg_sequential_workspace(n) bytes
+        (else one is allocated here, on the output's device)."""
+        if out.dtype != torch.float64:
+            raise ValueError("sequential fills are float64")
+        if work is None and out.numel() > 0:
+            work = torch.empty(max(zg_sequential_workspace(out.numel()), 1), dtype=torch.uint8,
+                               device=out.device)
+        wp, wb = (None, 0) if work is None else (_ptr(work), work.numel() * work.element_size())
+        self._c(lib.zg_fill_sequential(self.h, _ptr(out), out.numel(), kind, seed & (2**64 - 1),
+                                       stream, first_word,
+                                       _ptr(next_word) if next_word is not None else None, wp,
+                                       wb, _stream(hip_stream)), "zg_fill_sequential")
         return out
 
     def zg_mutate(self, x, sigma, kind=ZG_SPLITMIX64, seed=0, stream=0, first_index=0,
@@ -463,3 +486,12 @@ class Server:
 
 __all__ = [n for n in dir() if n.startswith(("zg_", "ZG_"))] + ["Context", "Server", "ZgError",
                                                                  "lib"]
+
+
+def zg_sequential_workspace(n):
+    """Workspace bytes of a sequential fill of n variates."""
+    b = ctypes.c_uint64()
+    st = lib.zg_sequential_workspace(n, ctypes.byref(b))
+    if st != ZG_OK:
+        raise ZgError(st, "zg_sequential_workspace")
+    return int(b.value)

@@ -2,6 +2,8 @@
 // the graph-captured batch path and the launch-shape autotuner.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -262,6 +264,45 @@ zg_status zg_uniform_words(zg_ctx *ctx, uint64_t *d_out, uint64_t n, zg_kind kin
   return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "launch_words");
 }
 
+// ------------------------------------------------ sequential consumption
+
+// Positions the parallel pass scans for n variates, in whole workgroup spans:
+// the expected 1.041 n words, plus 0.9% of n and 16 sqrt(n) + 64 (the words
+// that n variates read have a standard deviation of about 0.26 sqrt(n)).
+static uint64_t seq_positions(uint64_t n) {
+  const uint64_t want = n + n / 20 + 16 * (uint64_t)std::sqrt((double)n) + 64;
+  return (want + SEQ_SPAN - 1) / SEQ_SPAN * SEQ_SPAN;
+}
+
+zg_status zg_sequential_workspace(uint64_t n, uint64_t *bytes) {
+  if (!bytes) return ZG_EINVAL;
+  *bytes = n ? (uint64_t)seq_work_bytes(seq_positions(n)) : 0;
+  return ZG_OK;
+}
+
+zg_status zg_fill_sequential(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kind, uint64_t seed,
+                             uint32_t stream, uint64_t first_word, uint64_t *d_next_word,
+                             void *d_work, uint64_t work_bytes, void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  if (kind != ZG_SPLITMIX64 && kind != ZG_JAVA_LCG48) return ZG_EINVAL;
+  if (n == 0) return ZG_OK;
+  if (!d_out || ((uintptr_t)d_out) % 8 || ((uintptr_t)d_next_word) % 8) return ZG_EINVAL;
+  if (stream >= max_streams_of(kind) || n > ZG_SEQ_MAX_N || !d_work) return ZG_EINVAL;
+  const uint64_t limit = window_of(kind);
+  uint64_t n_pos = seq_positions(n);
+  if (first_word >= limit || n_pos + 2 > limit - first_word) return ZG_ERANGE;
+  const uint64_t need = seq_work_bytes(n_pos);
+  if (work_bytes < need) return ZG_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->seq_spans && ctx->seq_spans * SEQ_SPAN < n_pos) n_pos = ctx->seq_spans * SEQ_SPAN;
+  }
+  DeviceGuard g(ctx->device);
+  SeqJob J{d_out, n, seed, first_word, n_pos, limit, d_next_word, stream, (uint32_t)kind};
+  const hipError_t e = launch_seq(J, ctx->d_tables, d_work, ctx->d_flags, (hipStream_t)hip_stream);
+  return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "launch_seq");
+}
+
 zg_status zg_decide_words(zg_ctx *ctx, const uint64_t *d_words, uint64_t n, uint8_t *d_class,
                           double *d_x, void *hip_stream) {
   if (!ctx) return ZG_EINVAL;
@@ -288,6 +329,12 @@ zg_status zg_set_test_knob(zg_ctx *ctx, int knob, int64_t value) {
   if (knob == ZG_KNOB_DMAX) {
     if (value < 1 || value > (int64_t)ZG_MAX_DRAWS) return ZG_EINVAL;
     ctx->dmax = (uint32_t)value;
+    return ZG_OK;
+  }
+  if (knob == ZG_KNOB_SEQ_SPANS) {
+    if (value < 0) return ZG_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->seq_spans = (uint64_t)value;
     return ZG_OK;
   }
   return ZG_EINVAL;

@@ -99,6 +99,7 @@ struct zg_ctx {
   uint32_t *d_flags = nullptr;
   uint64_t *d_counters = nullptr;
   uint32_t dmax = ZG_MAX_DRAWS;
+  uint64_t seq_spans = 0;             // test knob: cap on the sequential scan (0 = automatic)
   zg_tune tune[ZG_TUNE_CLASSES];
   std::vector<zg::HandleInfo> handles;
   uint32_t next_handle = 0;

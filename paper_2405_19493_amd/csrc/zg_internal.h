@@ -124,6 +124,48 @@ struct BatchHeader {
   uint64_t pad[6];
 };
 
+// Sequential consumption (one generator read in order): the parallel pass
+// scans positions in chunks of SEQ_CHUNK (one wave each), SEQ_WAVES chunks per
+// workgroup.
+constexpr uint32_t SEQ_WINDOWS = 16;                   // windows of 64 positions per chunk
+constexpr uint32_t SEQ_CHUNK = 64 * SEQ_WINDOWS;       // positions per chunk
+constexpr uint32_t SEQ_WAVES = 16;                     // chunks (waves) per workgroup
+constexpr uint64_t SEQ_SPAN = (uint64_t)SEQ_CHUNK * SEQ_WAVES;   // positions per workgroup
+constexpr uint64_t SEQ_FINISH_CAP = 1ull << 22;        // attempts of the sequential finish
+
+// Three-state map of a chunk (or of a workgroup's chunks in order): entered
+// at offset e (0..2) of its first position, the chain leaves it at offset
+// exit(e) of the next chunk's first position, having accepted cnt[e] attempts.
+struct SeqMap {
+  uint32_t cnt[3];
+  uint32_t exits;   // bits 2e..2e+1: exit(e)
+};
+// A workgroup's entry: the chain enters at offset e, and its first accepted
+// attempt is variate `base`.
+struct SeqEntry {
+  uint64_t base;
+  uint32_t e;
+  uint32_t pad;
+};
+// Result of the scan over all workgroups: accepted attempts in the scanned
+// positions, and the chain's entry offset past them.
+struct SeqHdr {
+  uint64_t total;
+  uint32_t exit;
+  uint32_t pad;
+};
+struct SeqJob {
+  double *out;
+  uint64_t n;           // variates wanted
+  uint64_t seed;
+  uint64_t first;       // word position of the first attempt
+  uint64_t n_pos;       // positions of the parallel pass (whole SEQ_SPANs)
+  uint64_t limit;       // word positions must stay below this (the index window)
+  uint64_t *next_word;  // device (may be null): position after the last word read
+  uint32_t s;           // stream
+  uint32_t kind;
+};
+
 // Host entry points of the device code (zg_kernels.hip).
 // resident: 0 = one workgroup per tile; k > 0 = a persistent grid of at most
 // k workgroups per CU (capped by occupancy) looping over the tiles.
@@ -134,6 +176,11 @@ hipError_t launch_words(uint64_t *out, uint64_t n, const DevTables *T, uint32_t 
                         uint64_t seed, uint32_t s, uint32_t d, uint64_t first, hipStream_t stream);
 hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, uint8_t *cls,
                          double *x, hipStream_t stream);
+// The four passes of a sequential fill (maps, scan, write, finish) on one
+// stream; `work` holds seq_work_bytes(n_pos) bytes.
+hipError_t launch_seq(const SeqJob &J, const DevTables *T, void *work, uint32_t *flags,
+                      hipStream_t stream);
+size_t seq_work_bytes(uint64_t n_pos);
 const void *kernel_reserve();
 const void *kernel_complete();
 // The kernel of a work class, and its dynamic LDS for `waves` waves.

@@ -1223,6 +1223,370 @@ __global__ __launch_bounds__(1024) void k_bpolar(DevRequest *R, const BatchHeade
   }
 }
 
+// ------------------------------------------------ sequential consumption
+//
+// The variates that successive nextGaussian(random) calls produce when every
+// call takes its words from one generator in order (Section 2, Listing 2).
+// Word p of the generator (position p) is W(seed, s, p, 0): for stream 0 the
+// SplittableRandom / Random sequence itself.  An attempt at position p reads
+// word p; a wedge test also reads word p+1 and the base strip words p+1 and
+// p+2; whatever the outcome, the next attempt starts at the next unread
+// position.  So the attempt starts form a chain p -> p + adv(p), adv in
+// {1, 2, 3} a function of word p alone, and variate k is the value of the
+// k-th accepting attempt on the chain from the first position.
+//
+// Since adv <= 3, the chain enters a chunk of positions at one of its first
+// three.  Pass 1 evaluates every attempt of its chunk (one wave, a window of
+// 64 positions per step, one per lane) and walks the chunk from each of the
+// three entries with scalar bit scans over the window's ballots, recording
+// the exit offset and the accepted count of each: the chunk's three-state
+// map.  Pass 2 (one workgroup) composes the workgroups' maps in order and
+// gives each workgroup its entry and its first output index.  Pass 3
+// composes within the workgroup, walks each chunk again from its true entry
+// and stores the accepted values at their ranks.  Pass 4, one lane, goes on
+// from the end of the scanned positions only if they held fewer than n
+// accepting attempts (the scan covers the expected count with a wide margin).
+
+// A lane's generator at position P = window base + lane: SplitMix64 keeps the
+// pre-mix counter word, the LCG the state of step 2 m + 1 of P's double.
+struct SeqLane {
+  uint64_t z;
+  uint64_t S1;
+};
+
+template <int KIND>
+DEV SeqLane seq_lane_at(const SeqJob &J, const DevTables *T, uint64_t P) {
+  SeqLane g;
+  if (KIND == ZG_JAVA_LCG48) {
+    g.z = 0;
+    g.S1 = lcg_jump(&T->lcg, lcg_state0(J.seed), 2 * lcg_index(J.s, P, 0) + 1);
+  } else {
+    g.z = J.seed + GAMMA * (1ull + ((uint64_t)J.s << 48) + P);
+    g.S1 = 0;
+  }
+  return g;
+}
+
+// The same for every lane of a window based at Pb (uniform): one jump per
+// window, then the lane's offset.
+template <int KIND>
+DEV SeqLane seq_window(const SeqJob &J, const DevTables *T, uint64_t Pb, uint32_t lane) {
+  SeqLane g;
+  if (KIND == ZG_JAVA_LCG48) {
+    const uint64_t Sb = lcg_jump(&T->lcg, lcg_state0(J.seed), 2 * lcg_index(J.s, Pb, 0) + 1);
+    g.z = 0;
+    g.S1 = aff(T->lcg.jump[0][2 * lane], Sb);
+  } else {
+    g.z = J.seed + GAMMA * (1ull + ((uint64_t)J.s << 48) + Pb) + GAMMA * (uint64_t)lane;
+    g.S1 = 0;
+  }
+  return g;
+}
+
+// Moves a lane's generator 64 positions on (the next window).
+template <int KIND>
+DEV void seq_advance(SeqLane &g, const DevTables *T) {
+  if (KIND == ZG_JAVA_LCG48)
+    g.S1 = aff(T->lcg.jump[0][128], g.S1);
+  else
+    g.z += GAMMA * 64ull;
+}
+
+// Word k positions after the lane's own (k = 0, 1, 2).
+template <int KIND>
+DEV uint64_t seq_word(const SeqLane &g, const DevTables *T, uint32_t k) {
+  if (KIND == ZG_JAVA_LCG48)
+    return lcg_word_from(k ? aff(T->lcg.jump[0][2 * k], g.S1) : g.S1);
+  return mix64(g.z + GAMMA * (uint64_t)k);
+}
+
+struct SeqAtt {
+  uint32_t adv;   // positions this attempt reads: 1 fast, 2 wedge, 3 base strip
+  bool acc;
+  double z;       // the signed value when accepted
+};
+
+// The attempt at the lane's position, with the arithmetic of resolve.
+template <int KIND>
+DEV SeqAtt seq_attempt(const LdsTabs &L, const DevTables *T, double r, const SeqLane &g) {
+  const uint64_t W = seq_word<KIND>(g, T, 0);
+  const uint32_t whi = (uint32_t)(W >> 32), wlo = (uint32_t)W;
+  const uint32_t i = whi >> 25;
+  const uint32_t neg = (whi >> 24) & 1u;
+  const Fast64 f = L.f64[i];
+  const uint32_t jh = j_hi(whi), jl = j_lo(whi, wlo);
+  const double x = to_f64(jh, jl) * f.w;
+  SeqAtt a;
+  a.adv = 1;
+  a.acc = true;
+  double xc = x;
+  if ((((uint64_t)jh << 32) | jl) >= f.k) {
+    const double u = u53(seq_word<KIND>(g, T, 1));
+    double thr, arg;
+    if (i == 0) {   // tail: x = r + a, a = -log(U1+)/r, accept U2 < exp(-a^2/2)
+      const double u1 = u53p(seq_word<KIND>(g, T, 1));
+      thr = u53(seq_word<KIND>(g, T, 2));
+      arg = -log(u1) / r;
+      xc = r + arg;
+      a.adv = 3;
+    } else {        // wedge: accept y[i-1] + U dy[i] < exp(-x^2/2)
+      const double2 yd = L.yd[i];
+      thr = yd.x + u * yd.y;
+      arg = x;
+      a.adv = 2;
+    }
+    a.acc = thr < exp(-0.5 * (arg * arg));
+  }
+  a.z = neg ? -xc : xc;
+  return a;
+}
+
+// The chain through one window: from offset cur (0..2, wave-uniform) it
+// takes every position up to the next slow attempt q, then jumps to q + adv(q).
+// Returns the mask of chain positions in the window and leaves cur at the
+// chain's offset in the next window.  slow, m3: ballots of adv >= 2, adv == 3.
+DEV uint64_t seq_walk(uint32_t &cur, uint64_t slow, uint64_t m3) {
+  uint64_t on = 0;
+  uint32_t c = cur;
+  while (c < 64) {
+    const uint64_t rem = slow & (~0ull << c);
+    if (rem == 0) {
+      on |= ~0ull << c;
+      c = 64;
+      break;
+    }
+    const uint32_t q = (uint32_t)__builtin_ctzll(rem);
+    on |= (~0ull << c) & ((2ull << q) - 1);   // positions c..q
+    c = q + 2 + (uint32_t)((m3 >> q) & 1ull);
+  }
+  cur = c - 64;
+  return on;
+}
+
+DEV uint32_t seq_exit(uint32_t exits, uint32_t e) { return (exits >> (2 * e)) & 3u; }
+
+// Element e (0..2) of a 3-entry array by selects (no indexed private memory).
+template <typename V>
+DEV V pick3(const V *a, uint32_t e) { return e == 0 ? a[0] : (e == 1 ? a[1] : a[2]); }
+
+// Pass 1: the three-state map of every chunk, and of every workgroup.
+template <int KIND>
+__global__ __launch_bounds__(1024) void k_seq_maps(SeqJob J, const DevTables *__restrict__ T,
+                                                   SeqMap *maps, SeqMap *wg_maps) {
+  __shared__ LdsTabs L;
+  __shared__ SeqMap wm[SEQ_WAVES];
+  load_tabs<OP_ZIG64>(T, L);
+  __syncthreads();
+  const uint32_t wave = uni(threadIdx.x >> 6), lane = lane_id();
+  const double r = T->r;
+  const uint64_t c = (uint64_t)blockIdx.x * SEQ_WAVES + wave;
+  SeqLane g = seq_window<KIND>(J, T, J.first + c * SEQ_CHUNK, lane);
+  uint32_t cur0 = 0, cur1 = 1, cur2 = 2, n0 = 0, n1 = 0, n2 = 0;
+  for (uint32_t w = 0; w < SEQ_WINDOWS; ++w) {
+    const SeqAtt a = seq_attempt<KIND>(L, T, r, g);
+    const uint64_t slow = __builtin_amdgcn_ballot_w64(a.adv != 1);
+    const uint64_t m3 = __builtin_amdgcn_ballot_w64(a.adv == 3);
+    const uint64_t macc = __builtin_amdgcn_ballot_w64(a.acc);
+    n0 += (uint32_t)__builtin_popcountll(seq_walk(cur0, slow, m3) & macc);
+    n1 += (uint32_t)__builtin_popcountll(seq_walk(cur1, slow, m3) & macc);
+    n2 += (uint32_t)__builtin_popcountll(seq_walk(cur2, slow, m3) & macc);
+    seq_advance<KIND>(g, T);
+  }
+  if (lane == 0) {
+    SeqMap m;
+    m.cnt[0] = n0;
+    m.cnt[1] = n1;
+    m.cnt[2] = n2;
+    m.exits = cur0 | (cur1 << 2) | (cur2 << 4);
+    maps[c] = m;
+    wm[wave] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SeqMap acc;
+    for (uint32_t e = 0; e < 3; ++e) {
+      uint32_t x = e, n = 0;
+      for (uint32_t w = 0; w < SEQ_WAVES; ++w) {
+        n += wm[w].cnt[x];
+        x = seq_exit(wm[w].exits, x);
+      }
+      acc.cnt[e] = n;
+      acc.exits = e ? acc.exits | (x << (2 * e)) : x;
+    }
+    wg_maps[blockIdx.x] = acc;
+  }
+}
+
+// A map with 64-bit counts, for the scan over workgroups.
+struct SeqMap64 {
+  uint64_t cnt[3];
+  uint32_t ex[3];
+  uint32_t pad;
+};
+
+DEV SeqMap64 seq_identity() {
+  SeqMap64 m;
+#pragma unroll
+  for (uint32_t e = 0; e < 3; ++e) {
+    m.cnt[e] = 0;
+    m.ex[e] = e;
+  }
+  m.pad = 0;
+  return m;
+}
+
+// a, then b
+DEV SeqMap64 seq_cat(const SeqMap64 &a, const SeqMap64 &b) {
+  SeqMap64 m;
+#pragma unroll
+  for (uint32_t e = 0; e < 3; ++e) {
+    const uint32_t x = a.ex[e];
+    m.cnt[e] = a.cnt[e] + pick3(b.cnt, x);
+    m.ex[e] = pick3(b.ex, x);
+  }
+  m.pad = 0;
+  return m;
+}
+
+DEV SeqMap64 seq_widen(const SeqMap &w) {
+  SeqMap64 m;
+#pragma unroll
+  for (uint32_t e = 0; e < 3; ++e) {
+    m.cnt[e] = w.cnt[e];
+    m.ex[e] = seq_exit(w.exits, e);
+  }
+  m.pad = 0;
+  return m;
+}
+
+// Pass 2 (one workgroup of 1024 threads): each thread composes a run of
+// workgroup maps, the runs are scanned in order, and each thread hands out
+// the entries of its run from the chain's start (offset 0, variate 0).
+__global__ __launch_bounds__(1024) void k_seq_scan(const SeqMap *wg_maps, uint32_t n_wg,
+                                                   SeqEntry *wg_entry, SeqHdr *hdr) {
+  __shared__ SeqMap64 sm[1024];
+  const uint32_t t = threadIdx.x, nt = blockDim.x;
+  const uint32_t per = (n_wg + nt - 1) / nt;
+  const uint32_t b = t * per < n_wg ? t * per : n_wg;
+  const uint32_t e_ = b + per < n_wg ? b + per : n_wg;
+  SeqMap64 m = seq_identity();
+  for (uint32_t k = b; k < e_; ++k) m = seq_cat(m, seq_widen(wg_maps[k]));
+  sm[t] = m;
+  __syncthreads();
+  for (uint32_t d = 1; d < nt; d <<= 1) {
+    SeqMap64 v = sm[t];
+    if (t >= d) v = seq_cat(sm[t - d], v);
+    __syncthreads();
+    sm[t] = v;
+    __syncthreads();
+  }
+  uint32_t ent = t ? sm[t - 1].ex[0] : 0u;
+  uint64_t base = t ? sm[t - 1].cnt[0] : 0ull;
+  for (uint32_t k = b; k < e_; ++k) {
+    SeqEntry E;
+    E.base = base;
+    E.e = ent;
+    E.pad = 0;
+    wg_entry[k] = E;
+    const SeqMap w = wg_maps[k];
+    base += pick3(w.cnt, ent);
+    ent = seq_exit(w.exits, ent);
+  }
+  if (t == nt - 1) {
+    SeqHdr H;
+    H.total = sm[t].cnt[0];
+    H.exit = sm[t].ex[0];
+    H.pad = 0;
+    *hdr = H;
+  }
+}
+
+// Pass 3: the values, at their ranks along the chain.
+template <int KIND>
+__global__ __launch_bounds__(1024) void k_seq_write(SeqJob J, const DevTables *__restrict__ T,
+                                                    const SeqMap *maps, const SeqEntry *wg_entry) {
+  __shared__ LdsTabs L;
+  __shared__ uint64_t wbase[SEQ_WAVES];
+  __shared__ uint32_t went[SEQ_WAVES];
+  load_tabs<OP_ZIG64>(T, L);
+  if (threadIdx.x == 0) {
+    const SeqEntry E = wg_entry[blockIdx.x];
+    uint64_t base = E.base;
+    uint32_t e = E.e;
+    for (uint32_t w = 0; w < SEQ_WAVES; ++w) {
+      wbase[w] = base;
+      went[w] = e;
+      const SeqMap m = maps[(uint64_t)blockIdx.x * SEQ_WAVES + w];
+      base += pick3(m.cnt, e);
+      e = seq_exit(m.exits, e);
+    }
+  }
+  __syncthreads();
+  const uint32_t wave = uni(threadIdx.x >> 6), lane = lane_id();
+  uint64_t base = uni64(wbase[wave]);
+  uint32_t cur = uni(went[wave]);
+  if (base >= J.n) return;
+  const double r = T->r;
+  const uint64_t c = (uint64_t)blockIdx.x * SEQ_WAVES + wave;
+  uint64_t Pb = J.first + c * SEQ_CHUNK;
+  SeqLane g = seq_window<KIND>(J, T, Pb, lane);
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (uint32_t w = 0; w < SEQ_WINDOWS; ++w) {
+    const SeqAtt a = seq_attempt<KIND>(L, T, r, g);
+    const uint64_t slow = __builtin_amdgcn_ballot_w64(a.adv != 1);
+    const uint64_t m3 = __builtin_amdgcn_ballot_w64(a.adv == 3);
+    const uint64_t macc = __builtin_amdgcn_ballot_w64(a.acc);
+    const uint64_t accm = seq_walk(cur, slow, m3) & macc;
+    if ((accm >> lane) & 1ull) {
+      const uint64_t k = base + (uint64_t)__builtin_popcountll(accm & below);
+      if (k < J.n) {
+        J.out[k] = a.z;
+        if (k == J.n - 1 && J.next_word) *J.next_word = Pb + lane + a.adv;
+      }
+    }
+    base += (uint64_t)__builtin_popcountll(accm);
+    if (base >= J.n) break;
+    Pb += 64;
+    seq_advance<KIND>(g, T);
+  }
+}
+
+// Pass 4 (one lane): only when the scanned positions held fewer than n
+// accepting attempts, the rest one attempt at a time from where the chain
+// left them; bounded by the index window and SEQ_FINISH_CAP attempts (then
+// the remaining variates are NaN and a flag is raised).
+template <int KIND>
+__global__ __launch_bounds__(64) void k_seq_finish(SeqJob J, const DevTables *__restrict__ T,
+                                                   const SeqHdr *hdr, uint32_t *flags) {
+  __shared__ LdsTabs L;
+  load_tabs<OP_ZIG64>(T, L);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const SeqHdr H = *hdr;
+  if (H.total >= J.n) return;
+  const double r = T->r;
+  uint64_t p = J.first + J.n_pos + H.exit;
+  uint64_t k = H.total;
+  uint64_t steps = 0;
+  while (k < J.n) {
+    if (p + 3 > J.limit) {
+      raise_flag(flags, ZG_FLAG_RANGE);
+      break;
+    }
+    if (steps >= SEQ_FINISH_CAP) {
+      raise_flag(flags, ZG_FLAG_BUDGET);
+      break;
+    }
+    const SeqLane g = seq_lane_at<KIND>(J, T, p);
+    const SeqAtt a = seq_attempt<KIND>(L, T, r, g);
+    if (a.acc) J.out[k++] = a.z;
+    p += a.adv;
+    ++steps;
+  }
+  for (; k < J.n; ++k) J.out[k] = nan64();
+  if (J.next_word) *J.next_word = p;
+}
+
 // ------------------------------------------------------------ host launch
 
 template <int OP, int KIND>
@@ -1327,6 +1691,48 @@ const void *kernel_batch_class(int cls) {
     case batch_class(OP_POLAR, ZG_SPLITMIX64): return (const void *)k_bpolar<ZG_SPLITMIX64>;
     default: return (const void *)k_bpolar<ZG_JAVA_LCG48>;
   }
+}
+
+// Workspace of a sequential fill over n_pos positions: chunk maps,
+// workgroup maps, workgroup entries and the scan result, 256-byte aligned.
+static size_t seq_align(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t seq_work_bytes(uint64_t n_pos) {
+  const uint64_t n_wg = n_pos / SEQ_SPAN;
+  return seq_align(n_wg * SEQ_WAVES * sizeof(SeqMap)) + seq_align(n_wg * sizeof(SeqMap)) +
+         seq_align(n_wg * sizeof(SeqEntry)) + seq_align(sizeof(SeqHdr));
+}
+
+template <int KIND>
+static hipError_t launch_seq_kind(const SeqJob &J, const DevTables *T, void *work,
+                                  uint32_t *flags, hipStream_t stream) {
+  const uint64_t n_wg = J.n_pos / SEQ_SPAN;
+  char *p = (char *)work;
+  SeqMap *maps = (SeqMap *)p;
+  p += seq_align(n_wg * SEQ_WAVES * sizeof(SeqMap));
+  SeqMap *wg_maps = (SeqMap *)p;
+  p += seq_align(n_wg * sizeof(SeqMap));
+  SeqEntry *wg_entry = (SeqEntry *)p;
+  p += seq_align(n_wg * sizeof(SeqEntry));
+  SeqHdr *hdr = (SeqHdr *)p;
+  const dim3 blk(64 * SEQ_WAVES);
+  if (n_wg)
+    hipLaunchKernelGGL((k_seq_maps<KIND>), dim3((uint32_t)n_wg), blk, 0, stream, J, T, maps,
+                       wg_maps);
+  hipLaunchKernelGGL(k_seq_scan, dim3(1), dim3(1024), 0, stream, (const SeqMap *)wg_maps,
+                     (uint32_t)n_wg, wg_entry, hdr);
+  if (n_wg)
+    hipLaunchKernelGGL((k_seq_write<KIND>), dim3((uint32_t)n_wg), blk, 0, stream, J, T,
+                       (const SeqMap *)maps, (const SeqEntry *)wg_entry);
+  hipLaunchKernelGGL((k_seq_finish<KIND>), dim3(1), dim3(64), 0, stream, J, T,
+                     (const SeqHdr *)hdr, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_seq(const SeqJob &J, const DevTables *T, void *work, uint32_t *flags,
+                      hipStream_t stream) {
+  if (J.kind == ZG_JAVA_LCG48) return launch_seq_kind<ZG_JAVA_LCG48>(J, T, work, flags, stream);
+  return launch_seq_kind<ZG_SPLITMIX64>(J, T, work, flags, stream);
 }
 
 size_t batch_class_lds_bytes(int cls, uint32_t waves) {

@@ -23,7 +23,8 @@ def test_header_declares_the_boundary():
     for need in ("zg_create", "zg_destroy", "zg_table", "zg_fill", "zg_fill_streams",
                  "zg_uniform_words", "zg_mutate", "zg_batch", "zg_stream_open", "zg_stream_fill",
                  "zg_server_create", "zg_server_submit", "zg_server_poll", "zg_server_destroy",
-                 "zg_error_flags", "zg_decide_words", "zg_strerror"):
+                 "zg_error_flags", "zg_decide_words", "zg_strerror", "zg_fill_sequential",
+                 "zg_sequential_workspace"):
         assert need in names, need
 
 
