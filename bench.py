@@ -135,6 +135,28 @@ def c3_lcg(ctx, Z, torch, steps, warmup):
                          "frac": 8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
+def sequential_row(ctx, Z, torch, steps, warmup):
+    """Sequential consumption: the variates successive nextGaussian(random)
+    calls take from one SplitMix64 generator (seed 7, stream 0), at the
+    largest size checked on the device (all four passes timed together)."""
+    n = Z.ZG_SEQ_MAX_N
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    work = torch.empty(Z.zg_sequential_workspace(n), dtype=torch.uint8, device="cuda")
+
+    def go():
+        ctx.zg_fill_sequential(out, kind=Z.ZG_SPLITMIX64, seed=7, stream=0, first_word=0,
+                               work=work)
+
+    ms, _, _ = time_kernel(go, steps, warmup, torch)
+    del out, work
+    return {"workload": f"sequential consumption, {n} FP64 variates from one SplitMix64 "
+                        "generator (seed 7, stream 0)",
+            "value": n / (ms * 1e-3), "unit": "variates/s", "ms": ms,
+            "roofline": {"bound": "hbm", "achieved": 8.0 * n / (ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": 8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
 def f32_row(ctx, Z, torch, steps, warmup):
     """The c2 layout in FP32 output (2^28 variates, 1 GiB; 4 B per variate)."""
     n = N_STREAMS * N_PER
@@ -339,6 +361,7 @@ def main():
     if not args.no_extra:
         line["f32"] = f32_row(ctx, Z, torch, args.steps, args.warmup)
         line["c3_lcg"] = c3_lcg(ctx, Z, torch, args.steps, args.warmup)
+        line["sequential"] = sequential_row(ctx, Z, torch, args.steps, args.warmup)
         line["c4_batch"] = c4_batch(ctx, Z, torch, 3)
     if args.serve_seconds > 0:
         from paper_2405_19493_amd import serve_bench
