@@ -291,6 +291,10 @@ zg_status zg_fill_sequential(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kin
   const uint64_t limit = window_of(kind);
   uint64_t n_pos = seq_positions(n);
   if (first_word >= limit || n_pos + 2 > limit - first_word) return ZG_ERANGE;
+  // Plans of more than SEQ_MAX_WG workgroups are refused: the two GPU faults
+  // seen on this path both had more (the scan then composes several maps per
+  // thread), and their cause is not known.  ZG_SEQ_MAX_N keeps plans at 66.
+  if (n_pos / SEQ_SPAN > SEQ_MAX_WG) return ZG_EINVAL;
   const uint64_t need = seq_work_bytes(n_pos);
   if (work_bytes < need) return ZG_EINVAL;
   {

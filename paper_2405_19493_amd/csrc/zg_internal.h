@@ -132,6 +132,7 @@ constexpr uint32_t SEQ_CHUNK = 64 * SEQ_WINDOWS;       // positions per chunk
 constexpr uint32_t SEQ_WAVES = 16;                     // chunks (waves) per workgroup
 constexpr uint64_t SEQ_SPAN = (uint64_t)SEQ_CHUNK * SEQ_WAVES;   // positions per workgroup
 constexpr uint64_t SEQ_FINISH_CAP = 1ull << 22;        // attempts of the sequential finish
+constexpr uint64_t SEQ_MAX_WG = 1024;                  // largest plan accepted (workgroups)
 
 // Three-state map of a chunk (or of a workgroup's chunks in order): entered
 // at offset e (0..2) of its first position, the chain leaves it at offset
