@@ -92,30 +92,47 @@ def median_ci(xs, z=3.29):
 
 def cpu_baseline(seconds):
     """The oracle (oracle/zg_oracle.c) on a bounded sample of the same workload:
-    whole streams of 4096 variates, seed 7, SplitMix64, one stream per call, the
-    calls spread over a thread pool of the host's cores (capped at 16, the CPU
-    share of one GPU), until about `seconds` of wall time have passed."""
-    from concurrent.futures import ThreadPoolExecutor
+    whole streams of 4096 variates, seed 7, SplitMix64, in batches of streams
+    whose variates the oracle's own threads share (one thread per host core,
+    capped at 16, the CPU share of one GPU), until about `seconds` of wall time
+    have passed."""
     from oracle import coracle as orc
     orc.build(force=False)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cores = max(1, min(cores, 16))
-    per_batch = 64 * cores
+    per_batch = 256 * cores
 
     def one(s):
         orc.fill_f64(orc.SM64, SEED, s, 0, N_PER, nthreads=1)
 
     s = 0
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=cores) as pool:
-        while time.perf_counter() - t0 < seconds and s < N_STREAMS:
-            list(pool.map(one, range(s, min(s + per_batch, N_STREAMS))))
-            s = min(s + per_batch, N_STREAMS)
+    while time.perf_counter() - t0 < seconds and s < N_STREAMS:
+        b = min(per_batch, N_STREAMS - s)
+        orc.fill_streams_f64(orc.SM64, SEED, s, b, 0, N_PER, nthreads=cores)
+        s += b
     dt = time.perf_counter() - t0
     done = s * N_PER
+    # one core, to set beside per-call times on a CPU (ns per variate)
+    k = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < min(3.0, seconds) and k < N_STREAMS:
+        one(k)
+        k += 1
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": done / dt, "unit": "variates/s", "cores": cores, "kind": "oracle",
+            "cpu": model,
             "sample": f"streams 0..{s - 1} of the 65536 x 4096 FP64 ziggurat variates "
-                      f"(SplitMix64 seed 7): {done} variates in {dt:.1f} s"}
+                      f"(SplitMix64 seed 7): {done} variates in {dt:.1f} s",
+            "one_core": {"value": k * N_PER / dt1, "unit": "variates/s",
+                         "ns_per_variate": dt1 * 1e9 / (k * N_PER),
+                         "sample": f"streams 0..{k - 1}, one thread"}}
 
 
 def c3_lcg(ctx, Z, torch, steps, warmup):

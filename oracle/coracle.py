@@ -95,6 +95,8 @@ def lib():
         L.orc_mutate.restype = u64
         L.orc_words.argtypes = [i32, u64, u32, u32, u64, u64, vp]
         L.orc_words.restype = None
+        L.orc_fill_streams_f64.argtypes = [vp, i32, u64, u32, u32, u64, u64, u32, vp, vp, i32]
+        L.orc_fill_streams_f64.restype = u64
         L.orc_seq_f64.argtypes = [vp, i32, u64, u32, u64, u64, vp, u64, vp, vp, vp, vp]
         L.orc_seq_f64.restype = u64
         _lib = L
@@ -174,6 +176,18 @@ def fill_f64(kind, seed, s, first, n, dmax=DMAX, nthreads=0):
     cls = np.empty(n, dtype=np.uint8)
     errs = lib().orc_fill_f64(ctypes.byref(table()), kind, seed & (2**64 - 1), s, first, n,
                               dmax, _p(out), _p(cls), _threads(nthreads))
+    return out, cls, int(errs)
+
+
+def fill_streams_f64(kind, seed, s0, n_streams, first, n_per, dmax=DMAX, nthreads=0):
+    """FP64 ziggurat variates first..first+n_per-1 of streams s0..s0+n_streams-1,
+    stream-major; returns (values, outcome codes, errors)."""
+    n = n_streams * n_per
+    out = np.empty(n, dtype=np.float64)
+    cls = np.empty(n, dtype=np.uint8)
+    errs = lib().orc_fill_streams_f64(ctypes.byref(table()), kind, seed & (2**64 - 1), s0,
+                                      n_streams, first, n_per, dmax, _p(out), _p(cls),
+                                      _threads(nthreads))
     return out, cls, int(errs)
 
 

@@ -358,16 +358,18 @@ typedef struct {
   double *out64;
   uint8_t *cls;
   uint64_t errors;
+  uint64_t n_per;   /* > 0: element k is variate first + k % n_per of stream s + k / n_per */
 } orc_job;
 
 static void *run_job(void *arg) {
   orc_job *J = (orc_job *)arg;
   uint64_t errs = 0;
   for (uint64_t k = J->lo; k < J->hi; ++k) {
-    uint64_t v = J->first + k;
+    uint64_t v = J->first + (J->n_per ? k % J->n_per : k);
+    uint32_t s = J->n_per ? J->s + (uint32_t)(k / J->n_per) : J->s;
     uint8_t c = 0;
     if (J->op == 0) {
-      ((double *)J->out)[k] = orc_zig_f64(J->T, J->kind, J->seed, J->s, v, J->dmax, &c);
+      ((double *)J->out)[k] = orc_zig_f64(J->T, J->kind, J->seed, s, v, J->dmax, &c);
     } else if (J->op == 1) {
       double x64;
       ((float *)J->out)[k] = orc_zig_f32(J->T, J->kind, J->seed, J->s, v, J->dmax, &c, &x64);
@@ -420,6 +422,15 @@ uint64_t orc_fill_f64(const orc_table *T, int kind, uint64_t seed, uint32_t s, u
                       uint64_t n, uint32_t dmax, double *out, uint8_t *cls, int nthreads) {
   orc_job j = {T, 0, kind, seed, s, first, 0, 0, dmax, 0.0, out, 0, cls, 0};
   return run_split(j, n, nthreads);
+}
+
+/* Streams s0 .. s0 + n_streams - 1, variates first .. first + n_per - 1 of
+ * each, stream-major in out (the multi-stream layout), split over nthreads. */
+uint64_t orc_fill_streams_f64(const orc_table *T, int kind, uint64_t seed, uint32_t s0,
+                              uint32_t n_streams, uint64_t first, uint64_t n_per, uint32_t dmax,
+                              double *out, uint8_t *cls, int nthreads) {
+  orc_job j = {T, 0, kind, seed, s0, first, 0, 0, dmax, 0.0, out, 0, cls, 0, n_per};
+  return run_split(j, (uint64_t)n_streams * n_per, nthreads);
 }
 
 uint64_t orc_fill_f32(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t first,
