@@ -1,0 +1,123 @@
+// The sequential-consumption passes (k_seq_maps, k_seq_scan, k_seq_write,
+// k_seq_finish) built from the kernel source for the host, with the shim in
+// tests/host/shim, and run through launch_seq:
+//   seq_emu N KIND SEED STREAM FIRST OUTFILE
+// writes the position after the last word read, then the N values.  Built
+// with AddressSanitizer, so that any access outside its buffer stops it.
+#include "hip/hip_runtime.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+
+thread_local uint3_ threadIdx;
+uint3_ blockIdx, blockDim, gridDim;
+std::vector<std::unique_ptr<EmuWave>> emu_waves;
+std::unique_ptr<std::barrier<>> emu_block_bar;
+
+namespace {
+// One pool of nt threads per block size, reused for every block.
+struct Pool {
+  explicit Pool(uint32_t n) : nt(n), start(n + 1), done(n + 1) {
+    for (uint32_t t = 0; t < nt; ++t)
+      th.emplace_back([this, t]() {
+        threadIdx = {t, 0, 0};
+        for (;;) {
+          start.arrive_and_wait();
+          if (quit) return;
+          (*body)();
+          done.arrive_and_wait();
+        }
+      });
+  }
+  ~Pool() {
+    quit = true;
+    start.arrive_and_wait();
+    for (auto &x : th) x.join();
+  }
+  uint32_t nt;
+  std::barrier<> start, done;
+  std::vector<std::thread> th;
+  const std::function<void()> *body = nullptr;
+  bool quit = false;
+};
+std::map<uint32_t, std::unique_ptr<Pool>> pools;
+}  // namespace
+
+void emu_run_grid(dim3 grid, dim3 block, const std::function<void()> &body) {
+  const uint32_t nt = block.x;
+  auto &pool = pools[nt];
+  if (!pool) pool = std::make_unique<Pool>(nt);
+  blockDim = {block.x, 1, 1};
+  gridDim = {grid.x, 1, 1};
+  pool->body = &body;
+  for (uint32_t b = 0; b < grid.x; ++b) {
+    blockIdx = {b, 0, 0};
+    emu_block_bar = std::make_unique<std::barrier<>>(nt);
+    emu_waves.clear();
+    for (uint32_t w = 0; w < (nt + 63) / 64; ++w) {
+      auto x = std::make_unique<EmuWave>();
+      x->bar = std::make_unique<std::barrier<>>(nt - 64 * w < 64 ? nt - 64 * w : 64);
+      emu_waves.push_back(std::move(x));
+    }
+    pool->start.arrive_and_wait();
+    pool->done.arrive_and_wait();
+  }
+}
+
+namespace zg {
+alignas(16) unsigned char s_polar[1 << 17];
+}
+
+#include "zg_table.cpp"
+#include "zg_kernels_emu.cpp"
+
+using namespace zg;
+
+int main(int argc, char **argv) {
+  if (argc < 7) return 2;
+  const uint64_t n = strtoull(argv[1], 0, 10);
+  const uint32_t kind = (uint32_t)atoi(argv[2]);
+  const uint64_t seed = strtoull(argv[3], 0, 10);
+  const uint32_t s = (uint32_t)atoi(argv[4]);
+  const uint64_t first = strtoull(argv[5], 0, 10);
+  zg_table_view tv;
+  if (build_table(&tv) != ZG_OK) return 2;
+  DevTables *T = new DevTables();
+  std::memset(T, 0, sizeof(*T));
+  for (int i = 0; i < ZG_LAYERS; ++i) {
+    T->fast64[i] = {tv.k53[i], tv.w53[i]};
+    T->fast32[i] = {tv.k24[i], tv.w24[i]};
+    T->y[i] = tv.y[i];
+    T->dy[i] = tv.dy[i];
+    T->w53[i] = tv.w53[i];
+    T->w24d[i] = tv.w24d[i];
+  }
+  T->r = tv.r;
+  build_lcg_tables(&T->lcg);
+  build_log_tables(&T->logt);
+  // the plan of zg_fill_sequential (without its size caps)
+  const uint64_t want = n + n / 20 + 16 * (uint64_t)std::sqrt((double)n) + 64;
+  const uint64_t n_pos = (want + SEQ_SPAN - 1) / SEQ_SPAN * SEQ_SPAN;
+  const uint64_t limit = kind == ZG_JAVA_LCG48 ? ZG_LCG_WINDOW : ZG_SM64_WINDOW;
+  double *out = (double *)malloc(n * sizeof(double));
+  uint64_t *next = (uint64_t *)malloc(sizeof(uint64_t));
+  uint32_t *flags = (uint32_t *)calloc(1, sizeof(uint32_t));
+  void *work = malloc(seq_work_bytes(n_pos));
+  std::fprintf(stderr, "n=%llu n_pos=%llu workgroups=%llu\n", (unsigned long long)n,
+               (unsigned long long)n_pos, (unsigned long long)(n_pos / SEQ_SPAN));
+  SeqJob J{out, n, seed, first, n_pos, limit, next, s, kind};
+  launch_seq(J, T, work, flags, nullptr);
+  FILE *f = fopen(argv[6], "wb");
+  if (!f) return 3;
+  fwrite(next, 8, 1, f);
+  fwrite(out, 8, n, f);
+  fclose(f);
+  free(out);
+  free(next);
+  free(flags);
+  free(work);
+  delete T;
+  pools.clear();
+  return 0;
+}

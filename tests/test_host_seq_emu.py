@@ -1,0 +1,62 @@
+"""The sequential passes' device source, built for the CPU with a HIP
+stand-in (tests/host/shim) and AddressSanitizer, at more than 1024
+workgroups (so the scan pass composes several workgroup maps per thread):
+every access stays in its buffer, and every value and the position after the
+last word read equal the oracle's sequential driver.  To reach that many
+workgroups at a size the CPU runs in seconds, the test build uses one window
+of 64 positions per chunk (the source with that one constant changed)."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "..", "paper_2405_19493_amd", "csrc")
+INCLUDE = os.path.join(HERE, "..", "include")
+
+
+def _prepare(dst):
+    k = open(os.path.join(CSRC, "zg_kernels.hip")).read()
+    k = k.replace("extern __shared__", "extern").replace("__shared__", "static")
+    k = k.replace("#include <hip/hip_runtime.h>", '#include "hip/hip_runtime.h"')
+    open(os.path.join(dst, "zg_kernels_emu.cpp"), "w").write(k)
+    h = open(os.path.join(CSRC, "zg_internal.h")).read()
+    h = h.replace('"../../include/zg.h"', '"zg.h"')
+    assert "constexpr uint32_t SEQ_WINDOWS = 16;" in h
+    h = h.replace("constexpr uint32_t SEQ_WINDOWS = 16;", "constexpr uint32_t SEQ_WINDOWS = 1;")
+    open(os.path.join(dst, "zg_internal.h"), "w").write(h)
+    for name, src in (("zg_table.cpp", CSRC), ("zg.h", INCLUDE)):
+        open(os.path.join(dst, name), "w").write(open(os.path.join(src, name)).read())
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    d = str(tmp_path_factory.mktemp("seq_emu"))
+    _prepare(d)
+    exe = os.path.join(d, "seq_emu")
+    r = subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address",
+                        "-fno-omit-frame-pointer", "-I", os.path.join(HERE, "host", "shim"),
+                        "-I", d, os.path.join(HERE, "host", "seq_emu.cpp"), "-o", exe,
+                        "-lpthread"], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail(r.stdout[-3000:] + r.stderr[-3000:])
+    return d, exe
+
+
+@pytest.mark.parametrize("kind,seed,s,first,n", [(1, 7, 0, 0, 1_000_000)])
+def test_sequential_source_beyond_1024_workgroups(emu, orc, kind, seed, s, first, n):
+    d, exe = emu
+    out = os.path.join(d, f"out_{kind}.bin")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+    r = subprocess.run([exe, str(n), str(kind), str(seed), str(s), str(first), out],
+                       capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, r.stderr[-4000:]
+    wg = int(r.stderr.split("workgroups=")[1].split()[0])
+    assert wg > 1024, r.stderr
+    raw = np.fromfile(out, dtype=np.uint64)
+    nxt, g = int(raw[0]), raw[1:]
+    o, cls, starts, o_next, fails = orc.seq_f64(kind, seed, s, first, n)
+    assert fails == 0
+    assert np.array_equal(g, o.view(np.uint64))
+    assert nxt == o_next
