@@ -1,5 +1,7 @@
 """Full-size GPU checks, in the launch configurations bench.py times:
 
+- every FP64 ziggurat variate of c2 (2^28) against the oracle, in the launch
+  shape the benchmark's autotuner picks;
 - sampled parity at 2^28 variates (c2 ziggurat and polar: 65536 streams x
   4096, SplitMix64 seed 7; c3: one LCG48 stream, seed 123456789): 2^16 random
   positions compared element by element with the oracle, under the rules of
@@ -41,6 +43,28 @@ def _oracle_at(kind, seed, positions, n_per, method=0):
             x, c, _ = orc.fill_f64(kind, seed, s, v, 1, nthreads=1)
             vals[k], cls[k] = x[0], c[0]
     return vals, cls
+
+
+def test_c2_full_parity_ziggurat(ctx, zg):
+    """Every one of the 2^28 FP64 ziggurat variates of the benchmark's workload
+    against the oracle (its multi-stream driver on the host's cores), with the
+    launch shape the benchmark's autotuner picks on MI355X: workgroup tiles of
+    1024 x 16 waves, at most 2 persistent workgroups per CU."""
+    n = N_STREAMS * N_PER
+    before = ctx.zg_get_tune(zg.ZG_TUNE_FILL_F64)
+    ctx.zg_set_tune(zg.ZG_TUNE_FILL_F64, 1024, 16, 2)
+    try:
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.zg_fill_streams(out, N_PER, N_STREAMS, kind=zg.ZG_SPLITMIX64, seed=7)
+        got = out.cpu().numpy()
+        del out
+        torch.cuda.empty_cache()
+    finally:
+        ctx.zg_set_tune(zg.ZG_TUNE_FILL_F64, *before)
+    want, cls, errs = orc.fill_streams_f64(orc.SM64, 7, 0, N_STREAMS, 0, N_PER, nthreads=16)
+    assert errs == 0
+    compare(got, want, cls, "c2 full")
+    assert ctx.zg_error_flags() == 0
 
 
 @pytest.mark.parametrize("method", [0, 1])
