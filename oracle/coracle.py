@@ -97,6 +97,10 @@ def lib():
         L.orc_words.restype = None
         L.orc_fill_streams_f64.argtypes = [vp, i32, u64, u32, u32, u64, u64, u32, vp, vp, i32]
         L.orc_fill_streams_f64.restype = u64
+        L.orc_fill_streams_f32.argtypes = [vp, i32, u64, u32, u32, u64, u64, u32, vp, vp, vp, i32]
+        L.orc_fill_streams_f32.restype = u64
+        L.orc_fill_streams_polar.argtypes = [i32, u64, u32, u32, u64, u64, u32, vp, vp, i32]
+        L.orc_fill_streams_polar.restype = u64
         L.orc_seq_f64.argtypes = [vp, i32, u64, u32, u64, u64, vp, u64, vp, vp, vp, vp]
         L.orc_seq_f64.restype = u64
         _lib = L
@@ -188,6 +192,30 @@ def fill_streams_f64(kind, seed, s0, n_streams, first, n_per, dmax=DMAX, nthread
     errs = lib().orc_fill_streams_f64(ctypes.byref(table()), kind, seed & (2**64 - 1), s0,
                                       n_streams, first, n_per, dmax, _p(out), _p(cls),
                                       _threads(nthreads))
+    return out, cls, int(errs)
+
+
+def fill_streams_f32(kind, seed, s0, n_streams, first, n_per, dmax=DMAX, nthreads=0):
+    """FP32 mode over streams s0..s0+n_streams-1, stream-major; returns (values f32,
+    FP64 value of the same decision, outcome codes, errors)."""
+    n = n_streams * n_per
+    out = np.empty(n, dtype=np.float32)
+    out64 = np.empty(n, dtype=np.float64)
+    cls = np.empty(n, dtype=np.uint8)
+    errs = lib().orc_fill_streams_f32(ctypes.byref(table()), kind, seed & (2**64 - 1), s0,
+                                      n_streams, first, n_per, dmax, _p(out), _p(out64), _p(cls),
+                                      _threads(nthreads))
+    return out, out64, cls, int(errs)
+
+
+def fill_streams_polar(kind, seed, s0, n_streams, first, n_per, dmax=DMAX, nthreads=0):
+    """Polar method over streams s0..s0+n_streams-1, stream-major; returns
+    (values, outcome codes, errors)."""
+    n = n_streams * n_per
+    out = np.empty(n, dtype=np.float64)
+    cls = np.empty(n, dtype=np.uint8)
+    errs = lib().orc_fill_streams_polar(kind, seed & (2**64 - 1), s0, n_streams, first, n_per,
+                                        dmax, _p(out), _p(cls), _threads(nthreads))
     return out, cls, int(errs)
 
 

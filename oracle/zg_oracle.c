@@ -372,16 +372,16 @@ static void *run_job(void *arg) {
       ((double *)J->out)[k] = orc_zig_f64(J->T, J->kind, J->seed, s, v, J->dmax, &c);
     } else if (J->op == 1) {
       double x64;
-      ((float *)J->out)[k] = orc_zig_f32(J->T, J->kind, J->seed, J->s, v, J->dmax, &c, &x64);
+      ((float *)J->out)[k] = orc_zig_f32(J->T, J->kind, J->seed, s, v, J->dmax, &c, &x64);
       if (J->out64) J->out64[k] = x64;
     } else if (J->op == 2) {
       double o1, o2;
       int att;
-      int ok = polar_pair(J->kind, J->seed, J->s, v >> 1, J->dmax, &o1, &o2, &att);
+      int ok = polar_pair(J->kind, J->seed, s, v >> 1, J->dmax, &o1, &o2, &att);
       ((double *)J->out)[k] = (v & 1) ? o2 : o1;
       c = (uint8_t)(ok ? ((att - 1 > 63 ? 63 : att - 1) << 2) : (3 | ((att - 1 > 63 ? 63 : att - 1) << 2)));
     } else {
-      double z = orc_zig_f64(J->T, J->kind, J->seed, J->s, v, J->dmax, &c);
+      double z = orc_zig_f64(J->T, J->kind, J->seed, s, v, J->dmax, &c);
       double *x = (double *)J->out;
       x[k] = x[k] + J->sigma * z;
     }
@@ -430,6 +430,22 @@ uint64_t orc_fill_streams_f64(const orc_table *T, int kind, uint64_t seed, uint3
                               uint32_t n_streams, uint64_t first, uint64_t n_per, uint32_t dmax,
                               double *out, uint8_t *cls, int nthreads) {
   orc_job j = {T, 0, kind, seed, s0, first, 0, 0, dmax, 0.0, out, 0, cls, 0, n_per};
+  return run_split(j, (uint64_t)n_streams * n_per, nthreads);
+}
+
+/* The same for the FP32 mode (out: float, out64: the FP64 value of the same
+ * decision) and for the polar method. */
+uint64_t orc_fill_streams_f32(const orc_table *T, int kind, uint64_t seed, uint32_t s0,
+                              uint32_t n_streams, uint64_t first, uint64_t n_per, uint32_t dmax,
+                              float *out, double *out64, uint8_t *cls, int nthreads) {
+  orc_job j = {T, 1, kind, seed, s0, first, 0, 0, dmax, 0.0, out, out64, cls, 0, n_per};
+  return run_split(j, (uint64_t)n_streams * n_per, nthreads);
+}
+
+uint64_t orc_fill_streams_polar(int kind, uint64_t seed, uint32_t s0, uint32_t n_streams,
+                                uint64_t first, uint64_t n_per, uint32_t dmax, double *out,
+                                uint8_t *cls, int nthreads) {
+  orc_job j = {0, 2, kind, seed, s0, first, 0, 0, dmax, 0.0, out, 0, cls, 0, n_per};
   return run_split(j, (uint64_t)n_streams * n_per, nthreads);
 }
 
