@@ -1,7 +1,8 @@
 """Full-size GPU checks, in the launch configurations bench.py times:
 
-- every FP64 ziggurat variate of c2 (2^28) against the oracle, in the launch
-  shape the benchmark's autotuner picks;
+- every variate of the benchmark's rows against the oracle: the c2 FP64
+  ziggurat (in the launch shape the benchmark's autotuner picks), the c2 polar
+  and FP32 fills, and the c3 LCG stream (2^28 each);
 - sampled parity at 2^28 variates (c2 ziggurat and polar: 65536 streams x
   4096, SplitMix64 seed 7; c3: one LCG48 stream, seed 123456789): 2^16 random
   positions compared element by element with the oracle, under the rules of
@@ -64,6 +65,48 @@ def test_c2_full_parity_ziggurat(ctx, zg):
     want, cls, errs = orc.fill_streams_f64(orc.SM64, 7, 0, N_STREAMS, 0, N_PER, nthreads=16)
     assert errs == 0
     compare(got, want, cls, "c2 full")
+    assert ctx.zg_error_flags() == 0
+
+
+def _full_stream_fill(ctx, zg, dtype, method):
+    tdt = torch.float32 if dtype == zg.ZG_F32 else torch.float64
+    out = torch.empty(N_STREAMS * N_PER, dtype=tdt, device="cuda")
+    ctx.zg_fill_streams(out, N_PER, N_STREAMS, method=method, kind=zg.ZG_SPLITMIX64, seed=7)
+    got = out.cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    return got
+
+
+def test_c2_full_parity_polar(ctx, zg):
+    """Every polar variate of the benchmark's c2 workload (2^28), within 4 ulp."""
+    got = _full_stream_fill(ctx, zg, zg.ZG_F64, zg.ZG_POLAR)
+    want, cls, errs = orc.fill_streams_polar(orc.SM64, 7, 0, N_STREAMS, 0, N_PER, nthreads=16)
+    assert errs == 0
+    compare(got, want, cls, "c2 polar full", polar=True)
+    assert ctx.zg_error_flags() == 0
+
+
+def test_c2_full_parity_f32(ctx, zg):
+    """Every FP32 variate of the benchmark's FP32 row (the c2 layout, 2^28)."""
+    got = _full_stream_fill(ctx, zg, zg.ZG_F32, zg.ZG_ZIGGURAT)
+    want, _, cls, errs = orc.fill_streams_f32(orc.SM64, 7, 0, N_STREAMS, 0, N_PER, nthreads=16)
+    assert errs == 0
+    compare(got, want, cls, "c2 f32 full")
+    assert ctx.zg_error_flags() == 0
+
+
+def test_c3_full_parity_lcg(ctx, zg):
+    """Every variate of the c3 row: 2^28 FP64 variates of one LCG48 stream."""
+    n = 1 << 28
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.zg_fill(out, kind=zg.ZG_JAVA_LCG48, seed=123456789, stream=0)
+    got = out.cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    want, cls, errs = orc.fill_f64(orc.LCG48, 123456789, 0, 0, n, nthreads=16)
+    assert errs == 0
+    compare(got, want, cls, "c3 full")
     assert ctx.zg_error_flags() == 0
 
 
