@@ -192,19 +192,30 @@ def f32_row(ctx, Z, torch, steps, warmup):
                          "frac": gbs / HBM_PEAK_GBS}}
 
 
-def c4_batch(ctx, Z, torch, reps):
-    """10^4 uneven requests (sizes clamp(2^(20u)), 70% FP64) plus one mutation
-    of 4096 x 1024 genes: one persistent batch launch against the same
-    requests issued one by one to the plain kernels."""
+def c4_recipe():
+    """The c4 request set: 10^4 sizes clamp(floor(2^(20u)), 1, 2^20) and FP64
+    with probability 0.7, u from numpy PCG64(4); request k is seed 1000 + k,
+    stream k, from index 0.  Plus one mutation of 4096 x 1024 genes (seed 999,
+    stream 0, sigma 0.1) whose initial genes are -5 + 10 U, U from the uniform
+    words of (seed 1, stream 65535)."""
     import numpy as np
     rng = np.random.Generator(np.random.PCG64(4))
     m = 10000
     u = rng.uniform(0.0, 1.0, m)
     sizes = np.clip(np.floor(2.0 ** (20 * u)).astype(np.int64), 1, 1 << 20)
     is64 = rng.uniform(0.0, 1.0, m) < 0.7
+    return sizes, is64, 4096 * 1024
+
+
+def c4_batch(ctx, Z, torch, reps):
+    """10^4 uneven requests (sizes clamp(2^(20u)), 70% FP64) plus one mutation
+    of 4096 x 1024 genes: one persistent batch launch against the same
+    requests issued one by one to the plain kernels."""
+    import numpy as np
+    sizes, is64, genes = c4_recipe()
+    m = sizes.size
     nbytes = [int(n) * (8 if f else 4) for n, f in zip(sizes, is64)]
     offs = np.concatenate([[0], np.cumsum([(b + 255) // 256 * 256 for b in nbytes])])
-    genes = 4096 * 1024
     pool = torch.empty(int(offs[-1]) + genes * 8 + 256, dtype=torch.uint8, device="cuda")
     views = []
     for k in range(m):

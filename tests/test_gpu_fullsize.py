@@ -160,3 +160,45 @@ def test_statistics_1e8(ctx, zg, dtype, kind):
     torch.cuda.empty_cache()
     assert np.all(np.isfinite(x))
     _check_normal(x, orc.table_dict()["r"], (str(dtype), kind))
+
+
+def test_c4_full_parity_batch(ctx, zg):
+    """The benchmark's c4 batch (10^4 uneven requests, 7.6e8 variates, plus the
+    4096 x 1024-gene mutation) in one zg_batch launch: every variate of every
+    request, and every mutated gene, against the oracle."""
+    import bench
+    sizes, is64, genes = bench.c4_recipe()
+    m = sizes.size
+    outs = [torch.empty(int(n), dtype=torch.float64 if f else torch.float32, device="cuda")
+            for n, f in zip(sizes, is64)]
+    # initial genes from the oracle's uniform words (the product's words equal them bit
+    # for bit, test_uniform_words_bit_exact)
+    w = orc.words(orc.SM64, 1, 65535, 0, 0, genes)
+    x0 = -5.0 + 10.0 * ((w >> np.uint64(11)).astype(np.float64) * 2.0 ** -53)
+    x = torch.from_numpy(x0.copy()).cuda()
+    reqs = [{"out": outs[k], "n": int(sizes[k]), "seed": 1000 + k, "stream": k,
+             "dtype": zg.ZG_F64 if is64[k] else zg.ZG_F32} for k in range(m)]
+    reqs.append({"out": x, "n": genes, "seed": 999, "stream": 0, "op": zg.ZG_OP_MUTATE,
+                 "sigma": 0.1, "dtype": zg.ZG_F64})
+    ctx.zg_batch(ctx.zg_batch_prepare(reqs))
+    torch.cuda.synchronize()
+    assert ctx.zg_error_flags() == 0
+    g64, w64, c64, g32, w32, c32 = [], [], [], [], [], []
+    for k in range(m):
+        got = outs[k].cpu().numpy()
+        if is64[k]:
+            want, cls, errs = orc.fill_f64(orc.SM64, 1000 + k, k, 0, int(sizes[k]),
+                                           nthreads=16 if sizes[k] > 65536 else 1)
+            g64.append(got); w64.append(want); c64.append(cls)
+        else:
+            want, _, cls, errs = orc.fill_f32(orc.SM64, 1000 + k, k, 0, int(sizes[k]),
+                                              nthreads=16 if sizes[k] > 65536 else 1)
+            g32.append(got); w32.append(want); c32.append(cls)
+        assert errs == 0
+    del outs
+    compare(np.concatenate(g64), np.concatenate(w64), np.concatenate(c64), "c4 f64")
+    compare(np.concatenate(g32), np.concatenate(w32), np.concatenate(c32), "c4 f32")
+    xm = x.cpu().numpy()
+    want, cls, errs = orc.mutate(x0, orc.SM64, 999, 0, 0, 0.1)
+    assert errs == 0
+    compare(xm, want, cls, "c4 mutation")
