@@ -211,8 +211,8 @@ zg_status zg_error_flags(zg_ctx *ctx, uint32_t *flags, int clear);
 /* Test knobs.  ZG_KNOB_DMAX: draw budget (1..256, default 256), so that a
  * test can force budget exhaustion from the host.  ZG_KNOB_SEQ_SPANS: caps
  * the positions the parallel pass of zg_fill_sequential scans at value x
- * 16384 (0 = automatic, the default), so that a test can make its
- * one-lane finish produce the rest. */
+ * 16384 (0 = automatic, the default; at most 1024), so that a test can make
+ * its one-lane finish produce the rest. */
 #define ZG_KNOB_DMAX 1
 #define ZG_KNOB_SEQ_SPANS 2
 zg_status zg_set_test_knob(zg_ctx *ctx, int knob, int64_t value);

@@ -336,7 +336,7 @@ zg_status zg_set_test_knob(zg_ctx *ctx, int knob, int64_t value) {
     return ZG_OK;
   }
   if (knob == ZG_KNOB_SEQ_SPANS) {
-    if (value < 0) return ZG_EINVAL;
+    if (value < 0 || value > (int64_t)SEQ_MAX_WG) return ZG_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->seq_spans = (uint64_t)value;
     return ZG_OK;
