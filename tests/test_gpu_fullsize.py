@@ -48,7 +48,7 @@ def _oracle_at(kind, seed, positions, n_per, method=0):
 
 def test_c2_full_parity_ziggurat(ctx, zg):
     """Every one of the 2^28 FP64 ziggurat variates of the benchmark's workload
-    against the oracle (its multi-stream driver on the host's cores), with the
+    against the oracle (its multi-stream routine on the host's cores), with the
     launch shape the benchmark's autotuner picks on MI355X: workgroup tiles of
     1024 x 16 waves, at most 2 persistent workgroups per CU."""
     n = N_STREAMS * N_PER

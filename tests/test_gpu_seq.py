@@ -1,5 +1,5 @@
 """Sequential consumption (one generator read in order) on the HIP path,
-against the oracle's sequential driver, through the C ABI.
+against the oracle's sequential routine, through the C ABI.
 
 Rules: tests/parity.py (fast path bit-exact, slow path <= 2 ulp).  Any
 accept-decision disagreement would shift every later variate, so the bar is

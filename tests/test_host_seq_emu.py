@@ -2,7 +2,7 @@
 stand-in (tests/host/shim) and AddressSanitizer, at more than 1024
 workgroups (so the scan pass composes several workgroup maps per thread):
 every access stays in its buffer, and every value and the position after the
-last word read equal the oracle's sequential driver.  To reach that many
+last word read equal the oracle's sequential routine.  To reach that many
 workgroups at a size the CPU runs in seconds, the test build uses one window
 of 64 positions per chunk (the source with that one constant changed)."""
 import os

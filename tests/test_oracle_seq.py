@@ -1,10 +1,10 @@
-"""Pins of the oracle's sequential-consumption driver: the variates that
+"""Pins of the oracle's sequential-consumption routine: the variates that
 successive nextGaussian(random) calls take from one generator in order
 (Section 2, Listing 2).  Each attempt reads one word, a wedge test one more
 and the base strip two more; a rejected attempt is followed by an attempt at
 the next unread word.
 
-The pins come from outside the driver: crafted word lists whose outcomes the
+The pins come from outside the routine: crafted word lists whose outcomes the
 table geometry fixes, the keyed oracle (separately pinned) at positions where
 the first attempt is fast, continuation across calls, and the mean number of
 words per variate against its closed form (Wald's identity with the

@@ -1,4 +1,4 @@
-"""The oracle's multi-stream batch driver (used by the benchmark's CPU
+"""The oracle's multi-stream batch routine (used by the benchmark's CPU
 baseline) gives exactly the per-stream variates, in stream-major order, for
 any thread count."""
 import numpy as np
