@@ -33,8 +33,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="approximate CPU work of the oracle baseline sample")
-    p.add_argument("--only", choices=["zig", "polar", "all"], default="all",
-                   help="restrict the timed kernels (for profiling runs)")
+    p.add_argument("--only", choices=["zig", "polar", "c4", "all"], default="all",
+                   help="restrict the timed kernels (for profiling runs; c4: only the batch row, "
+                        "printed as its own JSON line)")
     p.add_argument("--serve-seconds", type=float, default=5.0,
                    help="serving-loop run per mode (open-loop Poisson, 20k requests/s); 0 = skip")
     p.add_argument("--no-autotune", action="store_true",
@@ -311,6 +312,12 @@ def main():
         import tempfile
         cache = os.path.join(tempfile.gettempdir(), "zg_autotune_2p28.json")
         ctx.zg_autotune(cache, 8 * N_STREAMS * N_PER, use_cache=True)
+    if args.only == "c4":
+        row = c4_batch(ctx, Z, torch, 3)
+        row["batch_tune"] = list(ctx.zg_get_tune(Z.ZG_TUNE_BATCH))
+        ctx.close()
+        print(json.dumps({"c4_batch": row}), flush=True)
+        return
     tune = ctx.zg_get_tune(Z.ZG_TUNE_FILL_F64)
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     out.zero_()
