@@ -83,6 +83,12 @@ def lib():
         L.orc_zig_f64.restype = ctypes.c_double
         L.orc_decide_word.argtypes = [vp, u64, vp]
         L.orc_decide_word.restype = i32
+        L.orc_zig_f64_tape.argtypes = [vp, vp, u32, u32, vp, vp, u32, vp]
+        L.orc_zig_f64_tape.restype = ctypes.c_double
+        L.orc_attempt.argtypes = [vp, i32, u64, u64, u64, vp]
+        L.orc_attempt.restype = i32
+        L.orc_enum_attempt.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp]
+        L.orc_enum_attempt.restype = i32
         L.orc_polar_core.argtypes = [ctypes.c_double, ctypes.c_double, vp, vp]
         L.orc_polar_core.restype = i32
         L.orc_fill_f64.argtypes = [vp, i32, u64, u32, u64, u64, u32, vp, vp, i32]
@@ -247,10 +253,74 @@ def mutate(x, kind, seed, s, first, sigma, dmax=DMAX, nthreads=0):
     return y, cls, int(errs)
 
 
-def decide_word(W):
+def decide_word(W, L=None):
     x = ctypes.c_double()
-    c = lib().orc_decide_word(ctypes.byref(table()), W, ctypes.byref(x))
+    c = (L or lib()).orc_decide_word(ctypes.byref(table()), W, ctypes.byref(x))
     return int(c), x.value
+
+
+def zig_f64_tape(tape, dmax=DMAX, table_=None, L=None):
+    """One FP64 variate from crafted words (word d = tape[d], 0 past the end).
+    Returns (value, outcome code, list of the draw indices read in order)."""
+    L = L or lib()
+    arr = np.ascontiguousarray(tape, dtype=np.uint64)
+    reads = np.zeros(4 * dmax + 8, dtype=np.uint32)
+    nreads = ctypes.c_uint32()
+    cls = ctypes.c_uint8()
+    x = L.orc_zig_f64_tape(ctypes.byref(table_ or table()), _p(arr), arr.size, dmax,
+                           ctypes.byref(cls), _p(reads), reads.size, ctypes.byref(nreads))
+    return x, cls.value, reads[:min(nreads.value, reads.size)].tolist()
+
+
+def small_table(twin_table):
+    """The C table struct for a small twin table (n layers, thresholds and
+    widths at its j width); layers past n stay zero."""
+    T = OrcTable()
+    T.r = twin_table.r
+    for i in range(twin_table.n):
+        T.W[i] = twin_table.W[i]
+        T.y[i] = twin_table.y[i]
+        T.dy[i] = twin_table.dy[i]
+        T.w53[i] = twin_table.w[i]
+        T.k53[i] = twin_table.k[i]
+    return T
+
+
+def attempt(T, i, j, W1, W2, L=None):
+    """One attempt of the C oracle (orc_attempt): (code, x) with code 0 fast,
+    1 wedge accept, 2 tail accept, 5 wedge reject, 6 tail reject."""
+    x = ctypes.c_double()
+    c = (L or lib()).orc_attempt(ctypes.byref(T), i, j, W1, W2, ctypes.byref(x))
+    return int(c), x.value
+
+
+def enum_attempt(T, n, jbits, ubits, edges, L=None):
+    """Exhaustive enumeration of one attempt of the C oracle on a small table
+    (orc_enum_attempt).  Returns (accepted weight, accepted weight per bin of
+    |x|, accepted base-strip weight, total weight)."""
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    acc_bin = np.zeros(max(e.size - 1, 1), dtype=np.uint64)
+    out = np.zeros(3, dtype=np.uint64)
+    rc = (L or lib()).orc_enum_attempt(ctypes.byref(T), n, jbits, ubits, _p(e), e.size,
+                                       _p(acc_bin), _p(out))
+    if rc != 0:
+        raise AssertionError("base-strip decisions depend on j")
+    return int(out[0]), [int(c) for c in acc_bin], int(out[1]), int(out[2])
+
+
+def load_variant(path):
+    """Loads another build of the oracle source (a planted mistake in a copy,
+    for the mutant tests) with the same signatures."""
+    global _lib
+    saved = _lib
+    try:
+        _lib = None
+        src_lib = LIB
+        globals()["LIB"] = path
+        return lib()
+    finally:
+        globals()["LIB"] = src_lib
+        _lib = saved
 
 
 def polar_core(u1, u2):

@@ -113,63 +113,66 @@ def half_normal_cdf(x):
     return math.erf(x / math.sqrt(2.0))
 
 
-def enumerate_attempt_mass(T, jbits, ubits, edges):
-    """Exact enumeration of one attempt over every first word (layer i, j of
-    jbits bits) and every extra uniform on a grid of 2^ubits points.
+def enumerate_attempt_mass(T, jbits, ubits, edges, attempt_fn=None):
+    """Exhaustive enumeration of one attempt over every first word (layer i,
+    j of jbits bits) and every extra uniform on a grid of G = 2^ubits points,
+    each decision made by `attempt` itself (or by attempt_fn, same signature).
 
-    Every outcome has probability count / (n 2^jbits G^2) with G = 2^ubits;
-    counts are exact integers.  Returns (accepted count, accepted count per bin
-    of |x| between consecutive `edges`, accepted tail count, total count).
-    The sign bit only mirrors the output and is left out.  Counting uses the
-    same float arithmetic as `attempt`; the number of grid uniforms below a
-    threshold is found by a sorted search, which is exact because
-    y(U) = y_{i-1} + U dy_i is non-decreasing in U."""
-    import numpy as np
+    The grid uniforms are U = m/G and U+ = (m+1)/G.  Every outcome has
+    probability weight / (n 2^jbits G^2), with integer weights: a first word
+    weighs G^2, a wedge uniform G, a base-strip pair 1.  Returns (accepted
+    weight, accepted weight per bin of |x| between consecutive `edges`,
+    accepted base-strip weight, total weight).  The sign bit only mirrors the
+    output and is left out.  The base-strip decisions do not involve j: they
+    are enumerated for the first slow j of layer 0, checked equal for the last
+    one, and weighted by the number of slow j."""
+    fn = attempt_fn or attempt
     n = T.n
     G = 1 << ubits
-    us = np.arange(G, dtype=np.float64) * 2.0 ** -ubits
-    ups = (np.arange(G, dtype=np.float64) + 1.0) * 2.0 ** -ubits
-    edges = np.asarray(edges, dtype=np.float64)
+    J = 1 << jbits
     nb = len(edges) - 1
     per_bin = [0] * nb
     acc = 0
     tail_acc = 0
-    unit = G * G                  # weight of one first word
+    us = [m / G for m in range(G)]
+    ups = [(m + 1) / G for m in range(G)]
 
-    def put(xs, counts):
-        b = np.searchsorted(edges, xs, side="right") - 1
-        ok = (b >= 0) & (b < nb)
-        for bi, c in zip(b[ok].tolist(), counts[ok].tolist()):
-            per_bin[bi] += int(c)
+    def put(x, w):
+        for b in range(nb):
+            if edges[b] <= x < edges[b + 1]:
+                per_bin[b] += w
+                return
 
-    # tail attempt: independent of j; accepted U2 count per U1 grid point
-    a = np.array([-math.log(u) / T.r for u in ups.tolist()])
-    lim = np.array([math.exp(-0.5 * (t * t)) for t in a.tolist()])
-    tail_cnt = np.searchsorted(us, lim, side="left").astype(np.int64)   # #{U2 < lim}
-    tail_x = T.r + a
-    js = np.arange(1 << jbits, dtype=np.int64)
+    def u_of(u):
+        return u
+
     for i in range(n):
-        xs = js.astype(np.float64) * T.w[i]
-        fast = js < T.k[i]
-        nf = int(fast.sum())
-        acc += nf * unit
-        put(xs[fast], np.full(nf, unit, dtype=np.int64))
-        nslow = (1 << jbits) - nf
-        if nslow == 0:
-            continue
-        if i == 0:
-            total_tail = int(tail_cnt.sum())
-            acc += nslow * total_tail
-            tail_acc += nslow * total_tail
-            put(tail_x, tail_cnt * nslow)
-        else:
-            yv = T.y[i - 1] + us * T.dy[i]
-            xsl = xs[~fast]
-            lims = np.array([math.exp(-0.5 * (x * x)) for x in xsl.tolist()])
-            cnt = np.searchsorted(yv, lims, side="left").astype(np.int64)  # #{y(U) < lim}
-            acc += int(cnt.sum()) * G
-            put(xsl, cnt * G)
-    total = n * (1 << jbits) * unit
+        slow = []
+        for j in range(J):
+            out, x = fn(T, i, j, 0.5, 0.5, u_of, u_of)
+            if out == "fast":
+                acc += G * G
+                put(x, G * G)
+                continue
+            slow.append(j)
+            if i == 0:
+                continue
+            for u in us:
+                out, x = fn(T, i, j, u, None, u_of, u_of)
+                if out == "wedge_acc":
+                    acc += G
+                    put(x, G)
+        if i == 0 and slow:
+            for u1 in ups:
+                for u2 in us:
+                    out, x = fn(T, 0, slow[0], u1, u2, u_of, u_of)
+                    out_b, x_b = fn(T, 0, slow[-1], u1, u2, u_of, u_of)
+                    assert (out, x) == (out_b, x_b), "base-strip decision depends on j"
+                    if out == "tail_acc":
+                        acc += len(slow)
+                        tail_acc += len(slow)
+                        put(x, len(slow))
+    total = n * J * G * G
     return acc, per_bin, tail_acc, total
 
 

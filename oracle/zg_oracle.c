@@ -173,42 +173,71 @@ static uint8_t outcome(int path, int attempts) {
   return (uint8_t)(path | (a << 2));
 }
 
-/* Slow part of one attempt for layer i at draw d (the first word failed the
- * fast test).  x is the candidate from the first word (wedge only).  Returns
- * 1 and sets *xo on acceptance, 0 on rejection, -1 if the budget is hit;
- * *next_d receives the draw index of the next attempt. */
-static int slow_step(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t v,
-                     uint32_t d, uint32_t dmax, int i, double x, double *xo, uint32_t *next_d,
-                     int *path) {
-  if (i == 0) {
-    if (d + 2 >= dmax) return -1;
-    double u1 = u53p(orc_word(kind, seed, s, v, d + 1));
-    double u2 = u53(orc_word(kind, seed, s, v, d + 2));
-    double a = -log(u1) / T->r;
-    double xt = T->r + a;
-    *next_d = d + 3;
-    *path = 2;
-    if (u2 < exp(-0.5 * (a * a))) {
-      *xo = xt;
-      return 1;
-    }
-    return 0;
-  }
-  if (d + 1 >= dmax) return -1;
-  double u = u53(orc_word(kind, seed, s, v, d + 1));
-  double y = T->y[i - 1] + u * T->dy[i];
-  *next_d = d + 2;
-  *path = 1;
-  if (y < exp(-0.5 * (x * x))) {
-    *xo = x;
-    return 1;
-  }
-  return 0;
+/* Where the words of one variate come from: word d is W(kind, seed, s, v, d),
+ * or tape[d] for kind 0 (crafted words for the tests).  When `reads` is set,
+ * every draw index read is appended to it (at most nreads_max entries). */
+typedef struct {
+  int kind;
+  uint64_t seed;
+  uint32_t s;
+  uint64_t v;
+  const uint64_t *tape;
+  uint32_t ntape;
+  uint32_t *reads;
+  uint32_t nreads, nreads_max;
+} orc_src;
+
+static uint64_t src_word(orc_src *S, uint32_t d) {
+  if (S->reads && S->nreads < S->nreads_max) S->reads[S->nreads] = d;
+  if (S->reads) S->nreads++;
+  if (S->kind == 0) return d < S->ntape ? S->tape[d] : 0;
+  return orc_word(S->kind, S->seed, S->s, S->v, d);
 }
 
-/* One FP64 standard normal for index v. */
-double orc_zig_f64(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t v,
-                   uint32_t dmax, uint8_t *cls) {
+/* The three steps of one attempt of the original ziggurat.  They are the only
+ * place where the oracle decides anything; every driver below (keyed FP64,
+ * FP32, mutation, sequential consumption, crafted words, tiny tables) calls
+ * them, so the tests that enumerate them pin every driver.
+ *
+ * 1. Decode of the first word: layer = top 7 bits, sign = bit 56, j = bits 3..55. */
+static void decode64(uint64_t W, int *i, int *neg, uint64_t *j) {
+  *i = (int)(W >> 57);
+  *neg = (int)((W >> 56) & 1);
+  *j = (W >> 3) & ((1ULL << 53) - 1);
+}
+
+/* 2. Fast test inside the layer's inner box: accept iff j < k53[i]; the
+ * candidate x = j * w53[i] is the point under the layer, used by the wedge. */
+static int fast_test(const orc_table *T, int i, uint64_t j, double *x) {
+  *x = (double)j * T->w53[i];
+  return j < T->k53[i];
+}
+
+/* 3. Slow part of an attempt whose first word failed the fast test, given the
+ * attempt's next words.  Base layer (i = 0), the exponential majorant beyond
+ * r: a = -log(U+ of W1)/r, candidate r + a, accept iff U of W2 < exp(-a^2/2).
+ * Other layers, the wedge: y = y[i-1] + U dy[i] with U from W1, accept the
+ * candidate x iff y < exp(-x^2/2).  Returns 1 and the accepted magnitude on
+ * acceptance, 0 on rejection. */
+static int slow_test(const orc_table *T, int i, double x, uint64_t W1, uint64_t W2, double *xo) {
+  if (i == 0) {
+    double a = -log(u53p(W1)) / T->r;
+    double xt = T->r + a;
+    *xo = xt;
+    return u53(W2) < exp(-0.5 * (a * a));
+  }
+  double y = T->y[i - 1] + u53(W1) * T->dy[i];
+  *xo = x;
+  return y < exp(-0.5 * (x * x));
+}
+
+/* Words an attempt of layer i reads after its first word, and so the draw
+ * offset of the next attempt after a rejection: 1 + 2 for the base layer,
+ * 1 + 1 for a wedge.  Every word is read once. */
+static uint32_t attempt_words(int i) { return i == 0 ? 3u : 2u; }
+
+/* One FP64 standard normal from a word source, draws 0 .. dmax-1. */
+static double zig_f64_src(const orc_table *T, orc_src *S, uint32_t dmax, uint8_t *cls) {
   uint32_t d = 0;
   int attempts = 0;
   for (;;) {
@@ -216,42 +245,147 @@ double orc_zig_f64(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint
       *cls = outcome(3, attempts + 1);
       return nan64();
     }
-    uint64_t W = orc_word(kind, seed, s, v, d);
-    int i = (int)(W >> 57);
-    int neg = (int)((W >> 56) & 1);
-    uint64_t j = (W >> 3) & ((1ULL << 53) - 1);
-    double x = (double)j * T->w53[i];
+    int i, neg;
+    uint64_t j;
+    double x;
+    decode64(src_word(S, d), &i, &neg, &j);
     attempts++;
-    if (j < T->k53[i]) {
+    if (fast_test(T, i, j, &x)) {
       *cls = outcome(0, attempts);
       return neg ? -x : x;
     }
-    double xo;
-    uint32_t nd;
-    int path;
-    int rc = slow_step(T, kind, seed, s, v, d, dmax, i, x, &xo, &nd, &path);
-    if (rc < 0) {
+    if (d + attempt_words(i) - 1 >= dmax) {
       *cls = outcome(3, attempts);
       return nan64();
     }
-    if (rc == 1) {
-      *cls = outcome(path, attempts);
+    uint64_t W1 = src_word(S, d + 1);
+    uint64_t W2 = i == 0 ? src_word(S, d + 2) : 0;
+    double xo;
+    if (slow_test(T, i, x, W1, W2, &xo)) {
+      *cls = outcome(i == 0 ? 2 : 1, attempts);
       return neg ? -xo : xo;
     }
-    d = nd;
+    d += attempt_words(i);
   }
+}
+
+/* One FP64 standard normal for index v. */
+double orc_zig_f64(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint64_t v,
+                   uint32_t dmax, uint8_t *cls) {
+  orc_src S = {kind, seed, s, v, 0, 0, 0, 0, 0};
+  return zig_f64_src(T, &S, dmax, cls);
+}
+
+/* One FP64 variate from crafted words tape[0..ntape) (word d = tape[d]; a
+ * word past the tape reads as 0).  reads (optional, nreads_max entries)
+ * receives the draw indices read, in order; returns their count in *nreads. */
+double orc_zig_f64_tape(const orc_table *T, const uint64_t *tape, uint32_t ntape, uint32_t dmax,
+                        uint8_t *cls, uint32_t *reads, uint32_t nreads_max, uint32_t *nreads) {
+  orc_src S = {0, 0, 0, 0, tape, ntape, reads, 0, nreads_max};
+  double x = zig_f64_src(T, &S, dmax, cls);
+  if (nreads) *nreads = S.nreads;
+  return x;
 }
 
 /* One attempt's class for a crafted first word (layer, sign, j decoded from W):
  * 0 fast, 1 wedge, 2 tail; *x is the first-word candidate (j * w53[i], signed). */
 int orc_decide_word(const orc_table *T, uint64_t W, double *x) {
-  int i = (int)(W >> 57);
-  int neg = (int)((W >> 56) & 1);
-  uint64_t j = (W >> 3) & ((1ULL << 53) - 1);
-  double xv = (double)j * T->w53[i];
+  int i, neg;
+  uint64_t j;
+  double xv;
+  decode64(W, &i, &neg, &j);
+  int fast = fast_test(T, i, j, &xv);
   *x = neg ? -xv : xv;
-  if (j < T->k53[i]) return 0;
+  if (fast) return 0;
   return i == 0 ? 2 : 1;
+}
+
+/* One attempt for a decoded first word (layer i, integer j) and the
+ * attempt's next words W1, W2, with T possibly a small table (only layers
+ * 0 .. n-1 used, k53 and w53 at any j width).  Returns 0 fast accept,
+ * 1 wedge accept, 2 tail accept, 5 wedge reject, 6 tail reject; *x the
+ * accepted or rejected magnitude.  For the exhaustive enumeration tests. */
+int orc_attempt(const orc_table *T, int i, uint64_t j, uint64_t W1, uint64_t W2, double *x) {
+  double xc;
+  if (fast_test(T, i, j, &xc)) {
+    *x = xc;
+    return 0;
+  }
+  int acc = slow_test(T, i, xc, W1, W2, x);
+  return (i == 0 ? 2 : 1) + (acc ? 0 : 4);
+}
+
+/* Exhaustive enumeration of one attempt on a table of n layers whose fast
+ * thresholds and widths are at jbits bits (k53[i] = floor(q_i 2^jbits),
+ * w53[i] = W_i 2^-jbits): every first word (layer i, j < 2^jbits; the sign
+ * only mirrors the output) and every extra uniform on the grid of
+ * G = 2^ubits points, U = m/G and U+ = (m+1)/G, each made into the word whose
+ * top ubits carry it.  Each decision is made by orc_attempt.  Outcome weights
+ * are integers: a first word weighs G^2, a wedge uniform G, a base-strip
+ * pair 1, out of n 2^jbits G^2 in all.  acc_bin[b] receives the accepted
+ * weight with edges[b] <= |x| < edges[b+1] (nedges edges); out[0] the
+ * accepted weight, out[1] the accepted base-strip weight, out[2] the total.
+ * The base-strip decisions do not involve j; they are enumerated for the
+ * first slow j of layer 0 and checked equal for the last, then weighted by
+ * the number of slow j.  Returns 0, or -1 if that check fails. */
+int orc_enum_attempt(const orc_table *T, int n, int jbits, int ubits, const double *edges,
+                     int nedges, uint64_t *acc_bin, uint64_t *out) {
+  const uint64_t G = 1ULL << ubits;
+  const uint64_t J = 1ULL << jbits;
+  const int sh = 64 - ubits;
+  uint64_t acc = 0, tail_acc = 0;
+  for (int b = 0; b + 1 < nedges; ++b) acc_bin[b] = 0;
+#define ORC_BIN(xv, wgt)                                              \
+  do {                                                                \
+    for (int b_ = 0; b_ + 1 < nedges; ++b_)                           \
+      if ((xv) >= edges[b_] && (xv) < edges[b_ + 1]) {                \
+        acc_bin[b_] += (wgt);                                         \
+        break;                                                        \
+      }                                                               \
+  } while (0)
+  for (int i = 0; i < n; ++i) {
+    uint64_t nslow = 0, j_first_slow = J, j_last_slow = 0;
+    for (uint64_t j = 0; j < J; ++j) {
+      double x;
+      if (orc_attempt(T, i, j, 0, 0, &x) == 0) {
+        acc += G * G;
+        ORC_BIN(x, G * G);
+        continue;
+      }
+      nslow++;
+      if (j_first_slow == J) j_first_slow = j;
+      j_last_slow = j;
+      if (i == 0) continue;
+      for (uint64_t m = 0; m < G; ++m) {
+        if (orc_attempt(T, i, j, m << sh, 0, &x) == 1) {
+          acc += G;
+          ORC_BIN(x, G);
+        }
+      }
+    }
+    if (i == 0 && nslow) {
+      for (uint64_t m1 = 0; m1 < G; ++m1) {
+        /* U+ = (m1 + 1)/G: the 53-bit field is (m1 + 1) 2^(53 - ubits) - 1 */
+        uint64_t W1 = ((((m1 + 1) << (53 - ubits)) - 1) << 11);
+        for (uint64_t m2 = 0; m2 < G; ++m2) {
+          double xa, xb;
+          int ra = orc_attempt(T, 0, j_first_slow, W1, m2 << sh, &xa);
+          int rb = orc_attempt(T, 0, j_last_slow, W1, m2 << sh, &xb);
+          if (ra != rb || (ra == 2 && xa != xb)) return -1;
+          if (ra == 2) {
+            acc += nslow;
+            tail_acc += nslow;
+            ORC_BIN(xa, nslow);
+          }
+        }
+      }
+    }
+  }
+#undef ORC_BIN
+  out[0] = acc;
+  out[1] = tail_acc;
+  out[2] = (uint64_t)n * J * G * G;
+  return 0;
 }
 
 /* FP32 output mode.  The attempt word is 32 bits: for the SplitMix64 kind the
@@ -290,22 +424,21 @@ float orc_zig_f32(const orc_table *T, int kind, uint64_t seed, uint32_t s, uint6
       return neg ? -xf : xf;
     }
     double x = (double)j * T->w24d[i];
-    double xo;
-    uint32_t nd;
-    int path;
-    int rc = slow_step(T, kind, seed, s, v, d, dmax, i, x, &xo, &nd, &path);
-    if (rc < 0) {
+    if (d + attempt_words(i) - 1 >= dmax) {
       *cls = outcome(3, attempts);
       *x64 = nan64();
       return nan32();
     }
-    if (rc == 1) {
+    uint64_t W1 = orc_word(kind, seed, s, v, d + 1);
+    uint64_t W2 = i == 0 ? orc_word(kind, seed, s, v, d + 2) : 0;
+    double xo;
+    if (slow_test(T, i, x, W1, W2, &xo)) {
       double sx = neg ? -xo : xo;
-      *cls = outcome(path, attempts);
+      *cls = outcome(i == 0 ? 2 : 1, attempts);
       *x64 = sx;
       return (float)sx;
     }
-    d = nd;
+    d += attempt_words(i);
   }
 }
 
@@ -507,43 +640,28 @@ static int gen_next(orc_gen *g, uint64_t *W) {
  * when the generator runs out first. */
 static int seq_variate(const orc_table *T, orc_gen *g, double *out, uint8_t *cls) {
   for (int att = 1;; ++att) {
-    uint64_t W, W1, W2;
+    uint64_t W, W1, W2 = 0;
     if (!gen_next(g, &W)) {
       *cls = outcome(3, att);
       break;
     }
-    int i = (int)(W >> 57);
-    int neg = (int)((W >> 56) & 1);
-    uint64_t j = (W >> 3) & ((1ULL << 53) - 1);
-    double x = (double)j * T->w53[i];
-    if (j < T->k53[i]) {
+    int i, neg;
+    uint64_t j;
+    double x, xo;
+    decode64(W, &i, &neg, &j);
+    if (fast_test(T, i, j, &x)) {
       *cls = outcome(0, att);
       *out = neg ? -x : x;
       return 1;
     }
-    if (i == 0) {
-      if (!gen_next(g, &W1) || !gen_next(g, &W2)) {
-        *cls = outcome(3, att);
-        break;
-      }
-      double a = -log(u53p(W1)) / T->r;
-      if (u53(W2) < exp(-0.5 * (a * a))) {
-        double xt = T->r + a;
-        *cls = outcome(2, att);
-        *out = neg ? -xt : xt;
-        return 1;
-      }
-    } else {
-      if (!gen_next(g, &W1)) {
-        *cls = outcome(3, att);
-        break;
-      }
-      double y = T->y[i - 1] + u53(W1) * T->dy[i];
-      if (y < exp(-0.5 * (x * x))) {
-        *cls = outcome(1, att);
-        *out = neg ? -x : x;
-        return 1;
-      }
+    if (!gen_next(g, &W1) || (i == 0 && !gen_next(g, &W2))) {
+      *cls = outcome(3, att);
+      break;
+    }
+    if (slow_test(T, i, x, W1, W2, &xo)) {
+      *cls = outcome(i == 0 ? 2 : 1, att);
+      *out = neg ? -xo : xo;
+      return 1;
     }
   }
   *out = nan64();

@@ -1,7 +1,7 @@
 """Comparison rules between the HIP path and the oracle.
 
-- Fast-path variates (accepted on the first word's integer test) must be
-  bit-identical, signed zeros included.
+- Fast-path variates (accepted by the integer test of a first word, on any
+  attempt) must be bit-identical, signed zeros included.
 - Variates accepted after a wedge or tail test must be within 2 ulp: the wedge
   value is exact by construction, the tail value goes through log, whose device
   and host implementations may differ by an ulp.
@@ -65,10 +65,10 @@ def compare(gpu, orc_vals, orc_cls, label="", polar=False):
         return dict(n=n, exact=n, slow_ulp_max=0, disagreements=0)
     eq = gpu.view(np.uint64 if gpu.dtype == np.float64 else np.uint32) == \
         orc_vals.view(np.uint64 if gpu.dtype == np.float64 else np.uint32)
-    fast = orc_cls == 0
-    # fast path: bit exact
-    bad_fast = np.flatnonzero(fast & ~eq)
     path = orc_cls & 3
+    fast = path == 0
+    # fast path (on any attempt): bit exact
+    bad_fast = np.flatnonzero(fast & ~eq)
     slow = ~fast & (path != 3)
     d = ulp_distance(gpu, orc_vals)
     nan_both = np.isnan(gpu) & np.isnan(orc_vals)
