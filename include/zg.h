@@ -219,16 +219,26 @@ zg_status zg_set_test_knob(zg_ctx *ctx, int knob, int64_t value);
 
 /* ------------------------------------------------ device-resident counters */
 
-/* A handle names one device counter slot bound to (seed, stream, kind);
- * counter = the next unused variate index.  Fills through a handle reserve
- * their index range on the device, in the order they are enqueued on the
- * context's control stream, so the bits never depend on timing. */
+/* A handle names one device counter slot bound to (seed, stream, kind) and
+ * to one output mode (dtype, method); counter = the next unused variate
+ * index.  Fills through a handle reserve their index range on the device, in
+ * the order they are enqueued, so the bits never depend on timing.
+ * The mode is fixed because the variate index maps to uniform words
+ * differently per mode (an FP32 variate pair shares one draw-0 word, a polar
+ * pair reads the draw-0 and draw-1 words of one index): consecutive ranges of
+ * one counter in different modes would read the same words again.  A
+ * ZG_OP_MUTATE request consumes FP64 ziggurat variates and so goes through a
+ * (ZG_F64, ZG_ZIGGURAT) handle.  Requests in another mode than the handle's
+ * are refused with ZG_EINVAL by zg_stream_fill, zg_batch and
+ * zg_server_submit.  zg_stream_open errors: ZG_EINVAL (null, enum, stream
+ * limit, ZG_F32 with ZG_POLAR), ZG_EBUSY (every slot open), ZG_EHIP. */
 typedef uint32_t zg_handle;
 #define ZG_MAX_HANDLES 65536u
 zg_status zg_stream_open(zg_ctx *ctx, uint64_t seed, uint32_t stream, zg_kind kind,
-                         zg_handle *out);
+                         zg_dtype dtype, zg_method method, zg_handle *out);
 zg_status zg_stream_close(zg_ctx *ctx, zg_handle h);
-/* Reserves [counter, counter + n) and fills d_out with those variates. */
+/* Reserves [counter, counter + n) and fills d_out with those variates;
+ * dtype and method must be the handle's. */
 zg_status zg_stream_fill(zg_ctx *ctx, zg_handle h, void *d_out, uint64_t n, zg_dtype dtype,
                          zg_method method, void *hip_stream);
 /* Checkpoint / resume: read (after all queued work) or set the counter. */
@@ -245,7 +255,13 @@ zg_status zg_stream_set_counter(zg_ctx *ctx, zg_handle h, uint64_t counter);
 /* One request of a batch.  op ZG_OP_FILL writes n variates to out (dtype,
  * method as zg_fill); ZG_OP_MUTATE applies zg_mutate to out (doubles, sigma).
  * handle >= 0 takes the first index from that device counter (and advances
- * it); otherwise first_index, seed, stream and kind are used as given. */
+ * it by n); otherwise first_index, seed, stream and kind are used as given.
+ * A counter-keyed request whose range would pass its stream's index window
+ * is skipped on the device (nothing written, ZG_FLAG_RANGE raised, its
+ * completion word carries the skip bit), and its range stays reserved: the
+ * counter still advances by n, so that the ranges of the batch's later
+ * requests on that handle, planned on the host, stay as planned.  The handle
+ * is then past its window until zg_stream_set_counter moves it back. */
 typedef struct zg_request {
   void *out;
   uint64_t n;
@@ -373,7 +389,8 @@ double zg_server_now(const zg_server *srv);
  * since the call, from the calling thread, so submission itself adds no
  * queueing; releases each output as soon as it completes (the arena then
  * bounds only the bytes in flight); returns once all have completed, or
- * ZG_EBUSY when timeout_s passes first.  first_out (host, optional, n
+ * ZG_EBUSY when timeout_s passes first (requests still running then are
+ * released by the server when they complete).  first_out (host, optional, n
  * entries) receives each request's first index.  Returns the first request
  * error seen, if any (the other requests still run). */
 zg_status zg_server_replay(zg_server *srv, const zg_server_request *reqs, uint32_t n,

@@ -142,7 +142,7 @@ def _load():
         "zg_decide_words": [P, P, U64, P, P, P],
         "zg_error_flags": [P, P, ctypes.c_int],
         "zg_set_test_knob": [P, ctypes.c_int, ctypes.c_int64],
-        "zg_stream_open": [P, U64, U32, ctypes.c_int, P],
+        "zg_stream_open": [P, U64, U32, ctypes.c_int, ctypes.c_int, ctypes.c_int, P],
         "zg_stream_close": [P, U32],
         "zg_stream_fill": [P, U32, P, U64, ctypes.c_int, ctypes.c_int, P],
         "zg_stream_get_counter": [P, U32, P],
@@ -324,10 +324,12 @@ class Context:
         self._c(lib.zg_set_test_knob(self.h, knob, value), "zg_set_test_knob")
 
     # ----------------------------------------------------------- counters
-    def zg_stream_open(self, seed, stream, kind=ZG_SPLITMIX64):
+    def zg_stream_open(self, seed, stream, kind=ZG_SPLITMIX64, dtype=ZG_F64, method=ZG_ZIGGURAT):
+        """A counter handle bound to (seed, stream, kind) and one output mode
+        (dtype, method); requests in another mode are refused."""
         h = ctypes.c_uint32()
-        self._c(lib.zg_stream_open(self.h, seed & (2**64 - 1), stream, kind, ctypes.byref(h)),
-                "zg_stream_open")
+        self._c(lib.zg_stream_open(self.h, seed & (2**64 - 1), stream, kind, dtype, method,
+                                   ctypes.byref(h)), "zg_stream_open")
         return h.value
 
     def zg_stream_close(self, handle):

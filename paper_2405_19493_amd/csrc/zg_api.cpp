@@ -347,10 +347,13 @@ zg_status zg_set_test_knob(zg_ctx *ctx, int knob, int64_t value) {
 // ------------------------------------------------------------- handles
 
 zg_status zg_stream_open(zg_ctx *ctx, uint64_t seed, uint32_t stream, zg_kind kind,
-                         zg_handle *out) {
+                         zg_dtype dtype, zg_method method, zg_handle *out) {
   if (!ctx || !out) return ZG_EINVAL;
   if (kind != ZG_SPLITMIX64 && kind != ZG_JAVA_LCG48) return ZG_EINVAL;
   if (stream >= max_streams_of(kind)) return ZG_EINVAL;
+  if ((dtype != ZG_F64 && dtype != ZG_F32) || (method != ZG_ZIGGURAT && method != ZG_POLAR) ||
+      (dtype == ZG_F32 && method == ZG_POLAR))
+    return ZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   for (uint32_t h = 0; h < ZG_MAX_HANDLES; ++h) {
     uint32_t k = (ctx->next_handle + h) % ZG_MAX_HANDLES;
@@ -359,7 +362,7 @@ zg_status zg_stream_open(zg_ctx *ctx, uint64_t seed, uint32_t stream, zg_kind ki
       uint64_t zero = 0;
       hipError_t e = hipMemcpy(ctx->d_counters + k, &zero, 8, hipMemcpyHostToDevice);
       if (e != hipSuccess) return hip_fail(ctx, e, "zg_stream_open");
-      ctx->handles[k] = {seed, stream, (uint32_t)kind, true};
+      ctx->handles[k] = {seed, stream, (uint32_t)kind, (uint32_t)dtype, (uint32_t)method, true};
       ctx->next_handle = k + 1;
       *out = k;
       return ZG_OK;

@@ -41,18 +41,20 @@ zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
     uint64_t seed = r.seed;
     uint32_t stream = r.stream;
     uint32_t kind = r.kind;
+    zg_dtype dt = r.op == ZG_OP_MUTATE ? ZG_F64 : (zg_dtype)r.dtype;
+    zg_method me = r.op == ZG_OP_MUTATE ? ZG_ZIGGURAT : (zg_method)r.method;
+    if (r.op == ZG_OP_MUTATE && (r.dtype != ZG_F64 || r.method != ZG_ZIGGURAT)) return ZG_EINVAL;
     if (r.handle >= 0) {
       if ((uint32_t)r.handle >= ZG_MAX_HANDLES || !ctx->handles[r.handle].open) return ZG_ENOENT;
       const HandleInfo &h = ctx->handles[r.handle];
+      // a counter serves one mode: another mode would read its words again
+      if (!handle_mode_ok(h, dt, me)) return ZG_EINVAL;
       seed = h.seed;
       stream = h.stream;
       kind = h.kind;
     } else if (r.handle != ZG_NO_HANDLE) {
       return ZG_EINVAL;
     }
-    zg_dtype dt = r.op == ZG_OP_MUTATE ? ZG_F64 : (zg_dtype)r.dtype;
-    zg_method me = r.op == ZG_OP_MUTATE ? ZG_ZIGGURAT : (zg_method)r.method;
-    if (r.op == ZG_OP_MUTATE && (r.dtype != ZG_F64 || r.method != ZG_ZIGGURAT)) return ZG_EINVAL;
     uint32_t op;
     // with a handle the first index is only known on the device: check the
     // shape here and the window there

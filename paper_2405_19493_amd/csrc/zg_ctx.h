@@ -16,8 +16,16 @@ struct HandleInfo {
   uint64_t seed;
   uint32_t stream;
   uint32_t kind;
+  uint32_t dtype;    // output mode the handle's counter serves
+  uint32_t method;
   bool open;
 };
+
+// Whether a request in (dtype, method) may use a handle: the mode decides
+// which uniform words a variate index reads, so a counter serves one mode.
+inline bool handle_mode_ok(const HandleInfo &h, uint32_t dtype, uint32_t method) {
+  return h.dtype == dtype && h.method == method;
+}
 
 // A validated batch ready for upload: only requests with n > 0, in order,
 // and the workgroup tiles of each work class.

@@ -52,6 +52,7 @@ struct Ticket {
   uint64_t off = 0;
   int32_t rec = -1;      // completion record while in flight
   bool has_mem = false;
+  bool detached = false; // released by the library once complete (nobody waits for it)
   zg_completion c{};
 };
 
@@ -132,9 +133,21 @@ struct zg_server {
   }
   void batch_loop();
   void complete_loop();
-  // Marks a request complete (lock held).
+  // Marks a request complete (lock held); a detached ticket is released and
+  // erased, so `t` must not be used afterwards.
   void finish(uint64_t id, Ticket &t, int32_t status, uint64_t first);
+  // Frees a complete ticket's output and forgets it (lock held).
+  void drop(std::unordered_map<uint64_t, Ticket>::iterator it);
 };
+
+void zg_server::drop(std::unordered_map<uint64_t, Ticket>::iterator it) {
+  if (it->second.has_mem) {
+    arena.release(it->second.off, it->second.bytes);
+    inflight_bytes -= it->second.bytes;
+  }
+  tickets.erase(it);
+  cv_work.notify_one();
+}
 
 void zg_server::finish(uint64_t id, Ticket &t, int32_t status, uint64_t first) {
   t.c.status = status;
@@ -151,13 +164,13 @@ void zg_server::finish(uint64_t id, Ticket &t, int32_t status, uint64_t first) {
     t.rec = -1;
     --n_inflight;
   }
-  (void)id;
   ++completed;
   if (status == ZG_OK) variates += t.req.n;
   latencies.push_back(t.c.complete_s - t.c.arrival_s);
   last_complete = std::max(last_complete, t.c.complete_s);
   cv_work.notify_one();
   cv_done.notify_all();
+  if (t.detached) drop(tickets.find(id));
 }
 
 void zg_server::batch_loop() {
@@ -368,6 +381,7 @@ zg_status zg_server_submit(zg_server *s, const zg_server_request *req, uint64_t 
   {
     std::lock_guard<std::mutex> hl(s->ctx->mu);
     if (req->handle >= ZG_MAX_HANDLES || !s->ctx->handles[req->handle].open) return ZG_ENOENT;
+    if (!handle_mode_ok(s->ctx->handles[req->handle], req->dtype, req->method)) return ZG_EINVAL;
   }
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return ZG_ESTATE;
@@ -418,14 +432,22 @@ zg_status zg_server_release(zg_server *s, uint64_t ticket) {
   auto it = s->tickets.find(ticket);
   if (it == s->tickets.end()) return ZG_ENOENT;
   if (!it->second.c.done) return ZG_EBUSY;
-  if (it->second.has_mem) {
-    s->arena.release(it->second.off, it->second.bytes);
-    s->inflight_bytes -= it->second.bytes;
-  }
-  s->tickets.erase(it);
-  s->cv_work.notify_one();
+  s->drop(it);
   return ZG_OK;
 }
+
+namespace {
+// Releases a ticket now if it is complete, else as soon as it completes.
+void release_when_done(zg_server *s, uint64_t ticket) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return;
+  if (it->second.c.done)
+    s->drop(it);
+  else
+    it->second.detached = true;
+}
+}  // namespace
 
 zg_status zg_server_drain(zg_server *s) {
   if (!s) return ZG_EINVAL;
@@ -461,12 +483,17 @@ zg_status zg_server_replay(zg_server *s, const zg_server_request *reqs, uint32_t
   if (!s || (n && !reqs)) return ZG_EINVAL;
   std::vector<uint64_t> tickets(n, 0);
   std::vector<char> ready(n, 0);
-  std::mutex rmu;
+  std::mutex rmu;   // ready[], result
   std::condition_variable rcv;
   zg_status result = ZG_OK;
+  auto note = [&](zg_status st) {   // keeps the first error
+    std::lock_guard<std::mutex> lk(rmu);
+    if (st != ZG_OK && result == ZG_OK) result = st;
+  };
   const double base = s->now();
   const double deadline = base + timeout_s;
-  // releases completed requests in submission order
+  // releases completed requests in submission order; a request still running
+  // at the deadline is released by the server when it completes
   std::thread releaser([&] {
     for (uint32_t k = 0; k < n; ++k) {
       {
@@ -478,11 +505,12 @@ zg_status zg_server_replay(zg_server *s, const zg_server_request *reqs, uint32_t
       const double left = deadline - s->now();
       zg_status st = left > 0 ? zg_server_wait(s, tickets[k], left, &c) : ZG_EBUSY;
       if (st != ZG_OK) {
-        result = st;
+        note(st);
+        release_when_done(s, tickets[k]);
         continue;
       }
       if (first_out) first_out[k] = c.first_index;
-      if (c.status != ZG_OK && result == ZG_OK) result = c.status;
+      note(c.status);
       zg_server_release(s, tickets[k]);
     }
   });
@@ -492,14 +520,15 @@ zg_status zg_server_replay(zg_server *s, const zg_server_request *reqs, uint32_t
     while (s->now() < r.arrival_s) {
     }
     zg_status st = zg_server_submit(s, &r, &tickets[k]);
+    note(st);
     {
       std::lock_guard<std::mutex> lk(rmu);
       ready[k] = st == ZG_OK ? 1 : -1;
-      if (st != ZG_OK && result == ZG_OK) result = st;
     }
     rcv.notify_one();
   }
   releaser.join();
+  std::lock_guard<std::mutex> lk(rmu);
   return result;
 }
 

@@ -3,8 +3,9 @@
 Requests arrive as a Poisson process (rate `rate` per second, inter-arrival
 times from numpy PCG64(5)); sizes are log-uniform in [16, 2^24] variates;
 70% FP64, 30% FP32; each request draws from one of a pool of counter handles
-(SplitMix64 streams), so a stream's requests continue where its previous one
-stopped.  Outputs go to the server's device arena and are released as soon as
+(SplitMix64 streams; 70% of the pool serves FP64 requests, the rest FP32,
+since a handle's counter serves one output mode), so a stream's requests
+continue where its previous one stopped.  Outputs go to the server's device arena and are released as soon as
 they complete (the admission cap bounds the bytes in flight).  Latency is
 completion time minus the scheduled arrival time, on the server clock.
 
@@ -32,8 +33,24 @@ def make_trace(rate, duration_s, n_handles, seed=5, min_n=16, max_n=1 << 24):
     sizes = np.exp(rng.uniform(np.log(min_n), np.log(max_n), m)).astype(np.int64)
     sizes = np.clip(sizes, min_n, max_n)
     dtypes = np.where(rng.uniform(0, 1, m) < 0.7, Z.ZG_F64, Z.ZG_F32)
-    handles = rng.integers(0, n_handles, m)
+    # a handle serves one dtype: the first 70% of the pool FP64, the rest FP32
+    n64 = handle_split(n_handles)
+    u = rng.uniform(0, 1, m)
+    handles = np.where(dtypes == Z.ZG_F64, (u * n64).astype(np.int64),
+                       n64 + (u * (n_handles - n64)).astype(np.int64))
     return t, sizes, dtypes, handles
+
+
+def handle_split(n_handles):
+    """Handles [0, n64) of the pool serve FP64 requests, the rest FP32."""
+    return max(1, min(n_handles - 1, (7 * n_handles) // 10))
+
+
+def open_handles(ctx, n_handles):
+    n64 = handle_split(n_handles)
+    return [ctx.zg_stream_open(1000 + h, h, Z.ZG_SPLITMIX64,
+                               dtype=Z.ZG_F64 if h < n64 else Z.ZG_F32)
+            for h in range(n_handles)]
 
 
 def run_mode(ctx, mode, trace, handles, mem_cap, sample, sample_n_max, seed_base, window_us,
@@ -141,7 +158,7 @@ def run(ctx, duration_s=5.0, rate=20000.0, n_handles=65536, mem_cap=64 << 30, wi
     out = {"offered_rate_per_s": rate, "duration_s": duration_s, "arena_bytes": mem_cap,
            "batch_window_us": window_us}
     modes = (("batched", Z.ZG_SERVE_BATCHED), ("per_request", Z.ZG_SERVE_PER_REQUEST))
-    handles = [ctx.zg_stream_open(1000 + h, h, Z.ZG_SPLITMIX64) for h in range(n_handles)]
+    handles = open_handles(ctx, n_handles)
     try:
         trace = make_trace(rate, duration_s, n_handles)
         out["requests"] = len(trace[0])

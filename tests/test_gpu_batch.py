@@ -115,13 +115,46 @@ def test_counters_continue_and_checkpoint(ctx, zg):
         ctx.zg_stream_set_counter(h, 1000)
         ctx.zg_stream_fill(h, b)
         assert host(b).tobytes() == w[1000:].tobytes()
-        # FP32 through a handle continues the same index space
+        # another mode would read the handle's words again: refused
         c = torch.empty(77, dtype=torch.float32, device="cuda")
-        ctx.zg_stream_fill(h, c)
-        want, _, cls, _ = orc.fill_f32(1, 123, 4, 3501, 77)
-        compare(host(c), want, cls, "handle f32")
+        with pytest.raises(zg.ZgError) as e:
+            ctx.zg_stream_fill(h, c)
+        assert e.value.status == zg.ZG_EINVAL
+        with pytest.raises(zg.ZgError) as e:
+            ctx.zg_stream_fill(h, a, method=zg.ZG_POLAR)
+        assert e.value.status == zg.ZG_EINVAL
+        assert ctx.zg_stream_get_counter(h) == 3501
     finally:
         ctx.zg_stream_close(h)
+
+
+def test_handle_modes(ctx, zg):
+    """FP32 and polar handles: each continues its own index space, and a
+    mutation goes through an FP64 ziggurat handle."""
+    h32 = ctx.zg_stream_open(seed=5, stream=2, kind=zg.ZG_SPLITMIX64, dtype=zg.ZG_F32)
+    hp = ctx.zg_stream_open(seed=6, stream=3, kind=zg.ZG_SPLITMIX64, method=zg.ZG_POLAR)
+    with pytest.raises(zg.ZgError) as e:
+        ctx.zg_stream_open(seed=6, stream=3, dtype=zg.ZG_F32, method=zg.ZG_POLAR)
+    assert e.value.status == zg.ZG_EINVAL
+    try:
+        c = torch.empty(77, dtype=torch.float32, device="cuda")
+        ctx.zg_stream_fill(h32, c)
+        ctx.zg_stream_fill(h32, c)
+        assert ctx.zg_stream_get_counter(h32) == 154
+        want, _, cls, _ = orc.fill_f32(1, 5, 2, 77, 77)
+        compare(host(c), want, cls, "handle f32")
+        p = torch.empty(1001, dtype=torch.float64, device="cuda")
+        ctx.zg_stream_fill(hp, p, method=zg.ZG_POLAR)
+        ctx.zg_stream_fill(hp, p, method=zg.ZG_POLAR)
+        whole = torch.empty(2002, dtype=torch.float64, device="cuda")
+        ctx.zg_fill(whole, method=zg.ZG_POLAR, seed=6, stream=3)
+        assert host(p).tobytes() == host(whole)[1001:].tobytes()
+        with pytest.raises(zg.ZgError) as e:
+            ctx.zg_batch([dict(out=p, n=1001, handle=h32, op=zg.ZG_OP_MUTATE, sigma=0.1)])
+        assert e.value.status == zg.ZG_EINVAL
+    finally:
+        ctx.zg_stream_close(h32)
+        ctx.zg_stream_close(hp)
 
 
 def test_batch_counters_follow_submission_order(ctx, zg):

@@ -10,10 +10,15 @@ from parity import compare
 pytestmark = pytest.mark.gpu
 
 
+def _handle_dtypes(n_handles):
+    """A handle serves one dtype: the last 2 of every 7 handles FP32 (1)."""
+    return np.array([1 if h % 7 >= 5 else 0 for h in range(n_handles)], dtype=np.int64)
+
+
 def _requests(rng, count, n_handles, max_log2=16):
     sizes = np.exp(rng.uniform(np.log(16), np.log(2 ** max_log2), count)).astype(np.int64)
-    dtypes = (rng.uniform(0, 1, count) >= 0.7).astype(np.int64)   # 1 = FP32
     hidx = rng.integers(0, n_handles, count)
+    dtypes = _handle_dtypes(n_handles)[hidx]
     return sizes, dtypes, hidx
 
 
@@ -22,7 +27,9 @@ def test_server_bits_and_counters(ctx, zg, mode):
     rng = np.random.Generator(np.random.PCG64(21 + mode))
     n_handles = 7
     seeds = [100 + h for h in range(n_handles)]
-    handles = [ctx.zg_stream_open(seeds[h], 10 + h, zg.ZG_SPLITMIX64) for h in range(n_handles)]
+    hdt = _handle_dtypes(n_handles)
+    handles = [ctx.zg_stream_open(seeds[h], 10 + h, zg.ZG_SPLITMIX64, dtype=int(hdt[h]))
+               for h in range(n_handles)]
     sizes, dtypes, hidx = _requests(rng, 150, n_handles)
     srv = zg.Server(ctx, mem_cap_bytes=64 << 20, max_inflight=64, max_batch=32,
                     batch_window_us=300, n_streams=2, mode=mode)
@@ -80,6 +87,9 @@ def test_server_admission_and_errors(ctx, zg):
         assert e.value.status == zg.ZG_EINVAL
         with pytest.raises(zg.ZgError) as e:
             srv.submit(h, 100, dtype=zg.ZG_F32, method=zg.ZG_POLAR)
+        assert e.value.status == zg.ZG_EINVAL
+        with pytest.raises(zg.ZgError) as e:
+            srv.submit(h, 100, dtype=zg.ZG_F32)         # the handle serves FP64
         assert e.value.status == zg.ZG_EINVAL
         with pytest.raises(zg.ZgError) as e:
             srv.submit(60000, 100)                      # not an open handle
