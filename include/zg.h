@@ -179,9 +179,9 @@ zg_status zg_mutate(zg_ctx *ctx, double *d_x, uint64_t n, double sigma, zg_kind 
  * zg_fill's, with no draw budget.
  * d_next_word (device, 8-byte aligned, or NULL) receives the position after
  * the last word read: passed back as first_word it continues the generator.
- * d_work: device workspace of work_bytes >= zg_sequential_workspace(n) bytes,
- * owned by the caller and in use until the call's work on hip_stream has
- * completed (the library allocates nothing here).
+ * d_work: device workspace (16-byte aligned) of work_bytes >=
+ * zg_sequential_workspace(n) bytes, owned by the caller and in use until the
+ * call's work on hip_stream has completed (the library allocates nothing).
  * d_out: n doubles, 8-byte aligned.  n = 0 does nothing.  Asynchronous.
  * n is limited to ZG_SEQ_MAX_N, the largest size checked on the device so far.
  * Errors: ZG_EINVAL (null, enum, alignment, stream limit, n > ZG_SEQ_MAX_N,

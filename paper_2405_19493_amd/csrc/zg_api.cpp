@@ -266,17 +266,9 @@ zg_status zg_uniform_words(zg_ctx *ctx, uint64_t *d_out, uint64_t n, zg_kind kin
 
 // ------------------------------------------------ sequential consumption
 
-// Positions the parallel pass scans for n variates, in whole workgroup spans:
-// the expected 1.041 n words, plus 0.9% of n and 16 sqrt(n) + 64 (the words
-// that n variates read have a standard deviation of about 0.26 sqrt(n)).
-static uint64_t seq_positions(uint64_t n) {
-  const uint64_t want = n + n / 20 + 16 * (uint64_t)std::sqrt((double)n) + 64;
-  return (want + SEQ_SPAN - 1) / SEQ_SPAN * SEQ_SPAN;
-}
-
 zg_status zg_sequential_workspace(uint64_t n, uint64_t *bytes) {
   if (!bytes) return ZG_EINVAL;
-  *bytes = n ? (uint64_t)seq_work_bytes(seq_positions(n)) : 0;
+  *bytes = n ? seq_plan(n).bytes : 0;
   return ZG_OK;
 }
 
@@ -288,22 +280,23 @@ zg_status zg_fill_sequential(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kin
   if (n == 0) return ZG_OK;
   if (!d_out || ((uintptr_t)d_out) % 8 || ((uintptr_t)d_next_word) % 8) return ZG_EINVAL;
   if (stream >= max_streams_of(kind) || n > ZG_SEQ_MAX_N || !d_work) return ZG_EINVAL;
+  if (((uintptr_t)d_work) % 16) return ZG_EINVAL;
   const uint64_t limit = window_of(kind);
-  uint64_t n_pos = seq_positions(n);
-  if (first_word >= limit || n_pos + 2 > limit - first_word) return ZG_ERANGE;
+  SeqPlan P = seq_plan(n);
+  if (first_word >= limit || P.n_pos + 2 > limit - first_word) return ZG_ERANGE;
   // Plans of more than SEQ_MAX_WG workgroups are refused: the two GPU faults
-  // seen on this path both had more (the scan then composes several maps per
-  // thread), and their cause is not known.  ZG_SEQ_MAX_N keeps plans at 66.
-  if (n_pos / SEQ_SPAN > SEQ_MAX_WG) return ZG_EINVAL;
-  const uint64_t need = seq_work_bytes(n_pos);
-  if (work_bytes < need) return ZG_EINVAL;
+  // seen on earlier builds of this path both had more, and their cause is
+  // not shown.  ZG_SEQ_MAX_N keeps plans at 66.
+  if (P.n_wg > SEQ_MAX_WG) return ZG_EINVAL;
+  if (work_bytes < P.bytes) return ZG_EINVAL;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->seq_spans && ctx->seq_spans * SEQ_SPAN < n_pos) n_pos = ctx->seq_spans * SEQ_SPAN;
+    if (ctx->seq_spans) P = seq_plan(n, ctx->seq_spans);
   }
   DeviceGuard g(ctx->device);
-  SeqJob J{d_out, n, seed, first_word, n_pos, limit, d_next_word, stream, (uint32_t)kind};
-  const hipError_t e = launch_seq(J, ctx->d_tables, d_work, ctx->d_flags, (hipStream_t)hip_stream);
+  SeqJob J{d_out, n, seed, first_word, P.n_pos, limit, d_next_word, stream, (uint32_t)kind};
+  const hipError_t e = launch_seq(J, P, ctx->d_tables, d_work, work_bytes, ctx->d_flags,
+                                  (hipStream_t)hip_stream);
   return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "launch_seq");
 }
 

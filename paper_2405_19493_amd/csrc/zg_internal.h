@@ -177,11 +177,28 @@ hipError_t launch_words(uint64_t *out, uint64_t n, const DevTables *T, uint32_t 
                         uint64_t seed, uint32_t s, uint32_t d, uint64_t first, hipStream_t stream);
 hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, uint8_t *cls,
                          double *x, hipStream_t stream);
+// The plan of a sequential fill of n variates: the positions its parallel
+// passes scan, their workgroups, and where each buffer lies in the
+// workspace.  seq_plan is the only place these are derived, for the size
+// query, the entry points and the launch alike, so the workspace is always
+// sized for the grid that writes it.
+struct SeqPlan {
+  uint64_t n_pos;     // positions scanned (whole SEQ_SPANs)
+  uint64_t n_wg;      // workgroups of the map and write passes: n_pos / SEQ_SPAN
+  uint64_t wg_cap;    // workgroups the buffers are sized for (>= n_wg)
+  uint64_t off_wg_maps, off_entry, off_hdr;   // byte offsets (chunk maps at 0)
+  uint64_t bytes;     // workspace bytes
+};
+// cap_wg > 0 scans at most cap_wg workgroups of positions (a test knob that
+// leaves the rest to the one-lane finish); the buffers keep the sizes of the
+// uncapped plan.
+SeqPlan seq_plan(uint64_t n, uint64_t cap_wg = 0);
 // The four passes of a sequential fill (maps, scan, write, finish) on one
-// stream; `work` holds seq_work_bytes(n_pos) bytes.
-hipError_t launch_seq(const SeqJob &J, const DevTables *T, void *work, uint32_t *flags,
-                      hipStream_t stream);
-size_t seq_work_bytes(uint64_t n_pos);
+// stream.  J.n_pos must be P.n_pos and `work` must hold P.bytes bytes; a plan
+// that does not fit its buffers is refused (hipErrorInvalidValue) before
+// anything is launched.
+hipError_t launch_seq(const SeqJob &J, const SeqPlan &P, const DevTables *T, void *work,
+                      uint64_t work_bytes, uint32_t *flags, hipStream_t stream);
 const void *kernel_reserve();
 const void *kernel_complete();
 // The kernel of a work class, and its dynamic LDS for `waves` waves.

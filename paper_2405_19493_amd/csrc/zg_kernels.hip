@@ -21,6 +21,7 @@
 // y = y[i-1] + U dy[i] must be rounded exactly as written.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "zg_internal.h"
@@ -1693,46 +1694,67 @@ const void *kernel_batch_class(int cls) {
   }
 }
 
-// Workspace of a sequential fill over n_pos positions: chunk maps,
-// workgroup maps, workgroup entries and the scan result, 256-byte aligned.
-static size_t seq_align(size_t b) { return (b + 255) / 256 * 256; }
+static uint64_t seq_align(uint64_t b) { return (b + 255) / 256 * 256; }
 
-size_t seq_work_bytes(uint64_t n_pos) {
-  const uint64_t n_wg = n_pos / SEQ_SPAN;
-  return seq_align(n_wg * SEQ_WAVES * sizeof(SeqMap)) + seq_align(n_wg * sizeof(SeqMap)) +
-         seq_align(n_wg * sizeof(SeqEntry)) + seq_align(sizeof(SeqHdr));
+// Positions scanned for n variates, in whole workgroup spans: the expected
+// 1.041 n words, plus 0.9% of n and 16 sqrt(n) + 64 (the words that n
+// variates read have a standard deviation of about 0.26 sqrt(n)).  The
+// workspace holds the chunk maps, the workgroup maps, the workgroup entries
+// and the scan result, each 256-byte aligned.
+SeqPlan seq_plan(uint64_t n, uint64_t cap_wg) {
+  SeqPlan P{};
+  const uint64_t want = n + n / 20 + 16 * (uint64_t)std::sqrt((double)n) + 64;
+  P.n_pos = (want + SEQ_SPAN - 1) / SEQ_SPAN * SEQ_SPAN;
+  P.n_wg = P.n_pos / SEQ_SPAN;
+  P.wg_cap = P.n_wg;
+  P.off_wg_maps = seq_align(P.wg_cap * SEQ_WAVES * sizeof(SeqMap));
+  P.off_entry = P.off_wg_maps + seq_align(P.wg_cap * sizeof(SeqMap));
+  P.off_hdr = P.off_entry + seq_align(P.wg_cap * sizeof(SeqEntry));
+  P.bytes = P.off_hdr + seq_align(sizeof(SeqHdr));
+  if (cap_wg && cap_wg < P.n_wg) {
+    P.n_wg = cap_wg;
+    P.n_pos = cap_wg * SEQ_SPAN;
+  }
+  return P;
+}
+
+// Whether every buffer of the plan lies inside a workspace of `bytes`.
+static bool seq_plan_fits(const SeqPlan &P, uint64_t bytes) {
+  return P.n_pos == P.n_wg * SEQ_SPAN && P.n_wg <= P.wg_cap &&
+         P.off_wg_maps >= P.wg_cap * SEQ_WAVES * sizeof(SeqMap) &&
+         P.off_entry >= P.off_wg_maps + P.wg_cap * sizeof(SeqMap) &&
+         P.off_hdr >= P.off_entry + P.wg_cap * sizeof(SeqEntry) &&
+         P.bytes >= P.off_hdr + sizeof(SeqHdr) && bytes >= P.bytes && P.n_wg < (1ull << 31);
 }
 
 template <int KIND>
-static hipError_t launch_seq_kind(const SeqJob &J, const DevTables *T, void *work,
-                                  uint32_t *flags, hipStream_t stream) {
-  const uint64_t n_wg = J.n_pos / SEQ_SPAN;
+static hipError_t launch_seq_kind(const SeqJob &J, const SeqPlan &P, const DevTables *T,
+                                  void *work, uint32_t *flags, hipStream_t stream) {
   char *p = (char *)work;
   SeqMap *maps = (SeqMap *)p;
-  p += seq_align(n_wg * SEQ_WAVES * sizeof(SeqMap));
-  SeqMap *wg_maps = (SeqMap *)p;
-  p += seq_align(n_wg * sizeof(SeqMap));
-  SeqEntry *wg_entry = (SeqEntry *)p;
-  p += seq_align(n_wg * sizeof(SeqEntry));
-  SeqHdr *hdr = (SeqHdr *)p;
+  SeqMap *wg_maps = (SeqMap *)(p + P.off_wg_maps);
+  SeqEntry *wg_entry = (SeqEntry *)(p + P.off_entry);
+  SeqHdr *hdr = (SeqHdr *)(p + P.off_hdr);
   const dim3 blk(64 * SEQ_WAVES);
-  if (n_wg)
-    hipLaunchKernelGGL((k_seq_maps<KIND>), dim3((uint32_t)n_wg), blk, 0, stream, J, T, maps,
+  if (P.n_wg)
+    hipLaunchKernelGGL((k_seq_maps<KIND>), dim3((uint32_t)P.n_wg), blk, 0, stream, J, T, maps,
                        wg_maps);
   hipLaunchKernelGGL(k_seq_scan, dim3(1), dim3(1024), 0, stream, (const SeqMap *)wg_maps,
-                     (uint32_t)n_wg, wg_entry, hdr);
-  if (n_wg)
-    hipLaunchKernelGGL((k_seq_write<KIND>), dim3((uint32_t)n_wg), blk, 0, stream, J, T,
+                     (uint32_t)P.n_wg, wg_entry, hdr);
+  if (P.n_wg)
+    hipLaunchKernelGGL((k_seq_write<KIND>), dim3((uint32_t)P.n_wg), blk, 0, stream, J, T,
                        (const SeqMap *)maps, (const SeqEntry *)wg_entry);
   hipLaunchKernelGGL((k_seq_finish<KIND>), dim3(1), dim3(64), 0, stream, J, T,
                      (const SeqHdr *)hdr, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_seq(const SeqJob &J, const DevTables *T, void *work, uint32_t *flags,
-                      hipStream_t stream) {
-  if (J.kind == ZG_JAVA_LCG48) return launch_seq_kind<ZG_JAVA_LCG48>(J, T, work, flags, stream);
-  return launch_seq_kind<ZG_SPLITMIX64>(J, T, work, flags, stream);
+hipError_t launch_seq(const SeqJob &J, const SeqPlan &P, const DevTables *T, void *work,
+                      uint64_t work_bytes, uint32_t *flags, hipStream_t stream) {
+  if (!work || J.n_pos != P.n_pos || !seq_plan_fits(P, work_bytes)) return hipErrorInvalidValue;
+  if (J.kind == ZG_JAVA_LCG48)
+    return launch_seq_kind<ZG_JAVA_LCG48>(J, P, T, work, flags, stream);
+  return launch_seq_kind<ZG_SPLITMIX64>(J, P, T, work, flags, stream);
 }
 
 size_t batch_class_lds_bytes(int cls, uint32_t waves) {

@@ -74,7 +74,59 @@ alignas(16) unsigned char s_polar[1 << 17];
 
 using namespace zg;
 
+// seq_emu scan N_WG SEED: the scan pass alone over N_WG synthetic workgroup
+// maps (random counts, random exits), against the maps composed in order one
+// at a time.  Prints "scan ok" or the first difference.
+static int scan_only(uint32_t n_wg, uint64_t seed) {
+  std::vector<SeqMap> maps(n_wg);
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+  auto next = [&x]() {
+    x ^= x << 13;
+    x ^= x >> 7;
+    x ^= x << 17;
+    return x;
+  };
+  for (auto &m : maps) {
+    for (int e = 0; e < 3; ++e) m.cnt[e] = (uint32_t)(next() % 20000);
+    m.exits = 0;
+    for (int e = 0; e < 3; ++e) m.exits |= (uint32_t)(next() % 3) << (2 * e);
+  }
+  // buffers of exactly the sizes the pass may touch, so that ASan sees any
+  // access outside them
+  SeqMap *d_maps = (SeqMap *)malloc(sizeof(SeqMap) * n_wg);
+  std::memcpy(d_maps, maps.data(), sizeof(SeqMap) * n_wg);
+  SeqEntry *d_ent = (SeqEntry *)malloc(sizeof(SeqEntry) * n_wg);
+  SeqHdr *d_hdr = (SeqHdr *)malloc(sizeof(SeqHdr));
+  hipLaunchKernelGGL(k_seq_scan, dim3(1), dim3(1024), 0, nullptr, (const SeqMap *)d_maps, n_wg,
+                     d_ent, d_hdr);
+  uint64_t base = 0;
+  uint32_t ent = 0;
+  int bad = 0;
+  for (uint32_t k = 0; k < n_wg && !bad; ++k) {
+    if (d_ent[k].base != base || d_ent[k].e != ent) {
+      std::fprintf(stderr, "workgroup %u: got (%llu, %u) want (%llu, %u)\n", k,
+                   (unsigned long long)d_ent[k].base, d_ent[k].e, (unsigned long long)base, ent);
+      bad = 1;
+    }
+    base += maps[k].cnt[ent];
+    ent = (maps[k].exits >> (2 * ent)) & 3u;
+  }
+  if (!bad && (d_hdr->total != base || d_hdr->exit != ent)) {
+    std::fprintf(stderr, "header: got (%llu, %u) want (%llu, %u)\n",
+                 (unsigned long long)d_hdr->total, d_hdr->exit, (unsigned long long)base, ent);
+    bad = 1;
+  }
+  free(d_maps);
+  free(d_ent);
+  free(d_hdr);
+  pools.clear();
+  if (!bad) std::printf("scan ok n_wg=%u total=%llu\n", n_wg, (unsigned long long)base);
+  return bad;
+}
+
 int main(int argc, char **argv) {
+  if (argc == 4 && std::strcmp(argv[1], "scan") == 0)
+    return scan_only((uint32_t)strtoul(argv[2], 0, 10), strtoull(argv[3], 0, 10));
   if (argc < 7) return 2;
   const uint64_t n = strtoull(argv[1], 0, 10);
   const uint32_t kind = (uint32_t)atoi(argv[2]);
@@ -96,18 +148,18 @@ int main(int argc, char **argv) {
   T->r = tv.r;
   build_lcg_tables(&T->lcg);
   build_log_tables(&T->logt);
-  // the plan of zg_fill_sequential (without its size caps)
-  const uint64_t want = n + n / 20 + 16 * (uint64_t)std::sqrt((double)n) + 64;
-  const uint64_t n_pos = (want + SEQ_SPAN - 1) / SEQ_SPAN * SEQ_SPAN;
+  // the plan of zg_fill_sequential (without its size caps), and a workspace
+  // of exactly its size
+  const SeqPlan P = seq_plan(n);
   const uint64_t limit = kind == ZG_JAVA_LCG48 ? ZG_LCG_WINDOW : ZG_SM64_WINDOW;
   double *out = (double *)malloc(n * sizeof(double));
   uint64_t *next = (uint64_t *)malloc(sizeof(uint64_t));
   uint32_t *flags = (uint32_t *)calloc(1, sizeof(uint32_t));
-  void *work = malloc(seq_work_bytes(n_pos));
+  void *work = malloc(P.bytes);
   std::fprintf(stderr, "n=%llu n_pos=%llu workgroups=%llu\n", (unsigned long long)n,
-               (unsigned long long)n_pos, (unsigned long long)(n_pos / SEQ_SPAN));
-  SeqJob J{out, n, seed, first, n_pos, limit, next, s, kind};
-  launch_seq(J, T, work, flags, nullptr);
+               (unsigned long long)P.n_pos, (unsigned long long)P.n_wg);
+  SeqJob J{out, n, seed, first, P.n_pos, limit, next, s, kind};
+  if (launch_seq(J, P, T, work, P.bytes, flags, nullptr) != hipSuccess) return 4;
   FILE *f = fopen(argv[6], "wb");
   if (!f) return 3;
   fwrite(next, 8, 1, f);

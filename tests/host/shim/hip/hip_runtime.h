@@ -36,6 +36,10 @@ inline float4 make_float4(float a, float b, float c, float d) { return {a, b, c,
 typedef int hipError_t;
 typedef void *hipStream_t;
 #define hipSuccess 0
+#define hipErrorInvalidValue 1
+#define hipErrorInvalidDevice 101
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) { *p = const_cast<void *>(sym); return 0; }
 #define hipDeviceAttributeMultiprocessorCount 1
 inline hipError_t hipGetLastError() { return 0; }
 inline hipError_t hipGetDevice(int *d) { *d = 0; return 0; }

@@ -60,3 +60,17 @@ def test_sequential_source_beyond_1024_workgroups(emu, orc, kind, seed, s, first
     assert fails == 0
     assert np.array_equal(g, o.view(np.uint64))
     assert nxt == o_next
+
+
+@pytest.mark.parametrize("n_wg", [1, 1024, 1025, 4096, 17220, 65536])
+def test_scan_pass_composes_many_maps_per_thread(emu, n_wg):
+    """The scan pass alone over synthetic workgroup maps (random counts and
+    exits), from one workgroup up to 64 maps per thread (17220 is the plan of
+    2^28 variates): each workgroup's entry and the scan total equal the maps
+    composed one at a time, and no access leaves its buffer."""
+    d, exe = emu
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+    r = subprocess.run([exe, "scan", str(n_wg), str(n_wg + 7)], capture_output=True, text=True,
+                       timeout=600, env=env)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert r.stdout.startswith(f"scan ok n_wg={n_wg}"), r.stdout
