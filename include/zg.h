@@ -198,6 +198,23 @@ zg_status zg_fill_sequential(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kin
 /* Workspace bytes zg_fill_sequential needs for n variates (0 for n = 0). */
 zg_status zg_sequential_workspace(uint64_t n, uint64_t *bytes);
 
+/* zg_fill_sequential without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the workspace is a device-resident
+ * array of the library, 8 MiB per GPU, held until the process ends; this
+ * call allocates nothing.  Same arguments, bits and errors as
+ * zg_fill_sequential, plus ZG_EINVAL for n above ZG_SEQ_NOALLOC_MAX_N (the
+ * workspace of larger n would not fit; ZG_SEQ_MAX_N applies as well) and
+ * ZG_ESTATE if the context could not resolve the array's address.  Every
+ * call on one GPU shares that array: calls whose work overlaps on one GPU
+ * (other streams, other contexts or threads) race and may write wrong
+ * values; order them on one stream or by events.  No part of the array needs
+ * clearing between calls (each call writes what it reads). */
+zg_status zg_fill_sequential_noalloc(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kind,
+                                     uint64_t seed, uint32_t stream, uint64_t first_word,
+                                     uint64_t *d_next_word, void *hip_stream);
+#define ZG_SEQ_NOALLOC_MAX_N 268435456ull
+
 /* Test hook: one ziggurat attempt per crafted word.  d_class[i] = 0 (fast),
  * 1 (wedge), 2 (tail); d_x[i] = the signed first-word candidate
  * (double)j * w53[i].  All pointers are device memory. */

@@ -37,6 +37,7 @@ ZG_FLAG_RANGE = 2
 ZG_KNOB_DMAX = 1
 ZG_KNOB_SEQ_SPANS = 2
 ZG_SEQ_MAX_N = 1000000
+ZG_SEQ_NOALLOC_MAX_N = 268435456
 ZG_OP_FILL = 0
 ZG_OP_MUTATE = 1
 ZG_NO_HANDLE = -1
@@ -137,6 +138,7 @@ def _load():
         "zg_fill_streams": [P, P, U64, U32, ctypes.c_int, ctypes.c_int, ctypes.c_int, U64, U32, U64, P],
         "zg_uniform_words": [P, P, U64, ctypes.c_int, U64, U32, U32, U64, P],
         "zg_fill_sequential": [P, P, U64, ctypes.c_int, U64, U32, U64, P, P, U64, P],
+        "zg_fill_sequential_noalloc": [P, P, U64, ctypes.c_int, U64, U32, U64, P, P],
         "zg_sequential_workspace": [U64, P],
         "zg_mutate": [P, P, U64, D, ctypes.c_int, U64, U32, U64, P],
         "zg_decide_words": [P, P, U64, P, P, P],
@@ -301,6 +303,18 @@ class Context:
                                        stream, first_word,
                                        _ptr(next_word) if next_word is not None else None, wp,
                                        wb, _stream(hip_stream)), "zg_fill_sequential")
+        return out
+
+    def zg_fill_sequential_noalloc(self, out, kind=ZG_SPLITMIX64, seed=0, stream=0,
+                                   first_word=0, next_word=None, hip_stream=None):
+        """zg_fill_sequential with the library's device-resident workspace
+        (nothing is allocated)."""
+        if out.dtype != torch.float64:
+            raise ValueError("sequential fills are float64")
+        self._c(lib.zg_fill_sequential_noalloc(
+            self.h, _ptr(out), out.numel(), kind, seed & (2**64 - 1), stream, first_word,
+            _ptr(next_word) if next_word is not None else None, _stream(hip_stream)),
+            "zg_fill_sequential_noalloc")
         return out
 
     def zg_mutate(self, x, sigma, kind=ZG_SPLITMIX64, seed=0, stream=0, first_index=0,

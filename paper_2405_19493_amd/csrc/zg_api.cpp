@@ -163,6 +163,7 @@ zg_status zg_create(int hip_device, zg_ctx **out) {
   if (e == hipSuccess) e = hipMemset(ctx->d_flags, 0, 64);
   if (e == hipSuccess) e = hipMalloc(&ctx->d_counters, sizeof(uint64_t) * ZG_MAX_HANDLES);
   if (e == hipSuccess) e = hipMemset(ctx->d_counters, 0, sizeof(uint64_t) * ZG_MAX_HANDLES);
+  if (e == hipSuccess) e = seq_scratch_ptr(hip_device, &ctx->d_seq_scratch);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     zg_destroy(ctx);
@@ -298,6 +299,17 @@ zg_status zg_fill_sequential(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kin
   const hipError_t e = launch_seq(J, P, ctx->d_tables, d_work, work_bytes, ctx->d_flags,
                                   (hipStream_t)hip_stream);
   return e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "launch_seq");
+}
+
+zg_status zg_fill_sequential_noalloc(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kind,
+                                     uint64_t seed, uint32_t stream, uint64_t first_word,
+                                     uint64_t *d_next_word, void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  if (n == 0) return ZG_OK;
+  if (n > ZG_SEQ_NOALLOC_MAX_N || seq_plan(n).bytes > SEQ_SCRATCH_BYTES) return ZG_EINVAL;
+  if (!ctx->d_seq_scratch) return ZG_ESTATE;
+  return zg_fill_sequential(ctx, d_out, n, kind, seed, stream, first_word, d_next_word,
+                            ctx->d_seq_scratch, SEQ_SCRATCH_BYTES, hip_stream);
 }
 
 zg_status zg_decide_words(zg_ctx *ctx, const uint64_t *d_words, uint64_t n, uint8_t *d_class,

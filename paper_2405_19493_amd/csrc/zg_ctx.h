@@ -106,6 +106,7 @@ struct zg_ctx {
   zg::DevTables *d_tables = nullptr;
   uint32_t *d_flags = nullptr;
   uint64_t *d_counters = nullptr;
+  void *d_seq_scratch = nullptr;      // the device's resident sequential workspace (not owned)
   uint32_t dmax = ZG_MAX_DRAWS;
   uint64_t seq_spans = 0;             // test knob: cap on the sequential scan (0 = automatic)
   zg_tune tune[ZG_TUNE_CLASSES];

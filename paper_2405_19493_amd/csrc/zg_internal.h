@@ -199,6 +199,11 @@ SeqPlan seq_plan(uint64_t n, uint64_t cap_wg = 0);
 // anything is launched.
 hipError_t launch_seq(const SeqJob &J, const SeqPlan &P, const DevTables *T, void *work,
                       uint64_t work_bytes, uint32_t *flags, hipStream_t stream);
+// Bytes of the device-resident sequential workspace (one per GPU).
+constexpr size_t SEQ_SCRATCH_BYTES = 8u << 20;
+// Device address of that workspace on device `dev`, which must be current;
+// resolved once per device (hipGetSymbolAddress) and kept.
+hipError_t seq_scratch_ptr(int dev, void **out);
 const void *kernel_reserve();
 const void *kernel_complete();
 // The kernel of a work class, and its dynamic LDS for `waves` waves.

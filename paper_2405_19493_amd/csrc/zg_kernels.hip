@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "zg_internal.h"
 
@@ -1692,6 +1693,36 @@ const void *kernel_batch_class(int cls) {
     case batch_class(OP_POLAR, ZG_SPLITMIX64): return (const void *)k_bpolar<ZG_SPLITMIX64>;
     default: return (const void *)k_bpolar<ZG_JAVA_LCG48>;
   }
+}
+
+// Device-resident workspace of the sequential fill that allocates nothing
+// (zg_fill_sequential_noalloc): each GPU the library runs on holds one copy
+// until the process ends.  Host code never passes this name to a kernel (on
+// the host it is a stand-in, not a device address): it uses the address that
+// seq_scratch_ptr resolved for the device.
+static __device__ __align__(256) unsigned char scratch[SEQ_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t seq_scratch_ptr(int dev, void **out) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev) return hipErrorInvalidDevice;   // the caller makes dev current
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_dev[dev] = ptr;
+  }
+  *out = scratch_dev[dev];
+  return hipSuccess;
 }
 
 static uint64_t seq_align(uint64_t b) { return (b + 255) / 256 * 256; }
