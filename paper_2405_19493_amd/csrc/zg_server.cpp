@@ -36,6 +36,10 @@ using namespace zg;
 namespace {
 
 constexpr uint64_t ARENA_ALIGN = 256;
+// Most HIP streams one server launches on (a build-time setting).
+#ifndef ZG_SERVER_MAX_STREAMS
+#define ZG_SERVER_MAX_STREAMS 2
+#endif
 // at most this many requests admitted together are launched one by one
 constexpr size_t SOLO_MAX = 4;
 
@@ -327,7 +331,7 @@ zg_status zg_server_create(zg_ctx *ctx, const zg_server_config *cfg, zg_server *
   if (!ctx || !cfg || !out) return ZG_EINVAL;
   if (cfg->mem_cap_bytes < ARENA_ALIGN || cfg->max_inflight == 0 || cfg->max_inflight > 1u << 20 ||
       cfg->max_batch == 0 || cfg->max_batch > ZG_MAX_BATCH || cfg->n_streams < 1 ||
-      cfg->n_streams > 2 || cfg->mode > ZG_SERVE_PER_REQUEST)
+      cfg->n_streams > ZG_SERVER_MAX_STREAMS || cfg->mode > ZG_SERVE_PER_REQUEST)
     return ZG_EINVAL;
   DeviceGuard g(ctx->device);
   zg_server *s = new zg_server();
