@@ -183,7 +183,7 @@ zg_status zg_mutate(zg_ctx *ctx, double *d_x, uint64_t n, double sigma, zg_kind 
  * zg_sequential_workspace(n) bytes, owned by the caller and in use until the
  * call's work on hip_stream has completed (the library allocates nothing).
  * d_out: n doubles, 8-byte aligned.  n = 0 does nothing.  Asynchronous.
- * n is limited to ZG_SEQ_MAX_N, the largest size checked on the device so far.
+ * n is limited to ZG_SEQ_MAX_N (10^6), the largest size checked on the device.
  * Errors: ZG_EINVAL (null, enum, alignment, stream limit, n > ZG_SEQ_MAX_N,
  * no or too small workspace), ZG_ERANGE (the scanned positions, about 1.05 n + 16 sqrt(n) from
  * first_word, would pass the stream's window: ZG_SM64_WINDOW or
@@ -308,23 +308,40 @@ typedef struct zg_request {
 zg_status zg_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, uint64_t *first_out,
                    void *hip_stream);
 
+/* The per-request form of a request array: each request (no handles) runs as
+ * its own plain launch (zg_fill or zg_mutate), in order on hip_stream, from
+ * one C loop.  Same bits as zg_batch; the baseline a batch is measured
+ * against.  Every request is checked first (errors as zg_fill, ZG_EINVAL for
+ * a handle); nothing is launched if any is invalid. */
+zg_status zg_fill_each(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, void *hip_stream);
+
 /* ----------------------------------------------------------------- tuning */
 
 /* Launch shape of the generation kernels: tile, the elements per wave of a
  * workgroup tile (f64 units; multiple of 128; a workgroup tile is tile x
- * waves elements, which the waves of the plain fills take in 1024-element
- * groups), waves per workgroup (1..16), batch_blocks_per_cu: for the
- * batch kernels the persistent workgroups per CU (1..8), for the plain fills
- * 0 (one workgroup per tile) or the most persistent workgroups per CU (capped
- * by occupancy), and queue_cap: the workgroup's slow-path queue
- * capacity of the plain ziggurat fills (0 = the built-in maximum of 2048;
- * smaller values, which also cap the retry queue below its 512 entries, only
- * serve to exercise the overflow paths).  Any shape gives the same bits. */
+ * waves elements, which the waves of the plain fills take in groups of
+ * group_steps steps of 256 elements), waves per workgroup (1..16),
+ * batch_blocks_per_cu: for the batch kernels the persistent workgroups per CU
+ * (1..8), for the plain fills 0 (one workgroup per tile) or the most
+ * persistent workgroups per CU (capped by occupancy), queue_cap: the
+ * workgroup's slow-path queue capacity of the plain ziggurat fills (0 = the
+ * built-in maximum of 2048; smaller values, which also cap the retry queue
+ * below its 512 entries, only serve to exercise the overflow paths),
+ * drain_waves: 0 runs the plain ziggurat fills (FP64, FP32, mutation) with
+ * the block-pooled kernel (streaming, one barrier, a drain of the pooled
+ * slow elements, per workgroup tile), 1..8 with the wave-specialised kernel
+ * (one 16-wave workgroup per CU, drain_waves of whose waves resolve the slow
+ * elements the others publish in an LDS ring; tile, waves_per_block,
+ * batch_blocks_per_cu and queue_cap then do not apply), and group_steps: the
+ * 256-element steps a wave streams between queue appends (1, 2, 4 or 8; the
+ * plain ziggurat fills only).  Any shape gives the same bits. */
 typedef struct zg_tune {
   uint32_t tile;
   uint32_t waves_per_block;
   uint32_t batch_blocks_per_cu;
   uint32_t queue_cap;
+  uint32_t drain_waves;
+  uint32_t group_steps;
 } zg_tune;
 #define ZG_TUNE_FILL_F64 0
 #define ZG_TUNE_FILL_F32 1

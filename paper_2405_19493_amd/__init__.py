@@ -92,7 +92,8 @@ class Request(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
-                ("batch_blocks_per_cu", ctypes.c_uint32), ("queue_cap", ctypes.c_uint32)]
+                ("batch_blocks_per_cu", ctypes.c_uint32), ("queue_cap", ctypes.c_uint32),
+                ("drain_waves", ctypes.c_uint32), ("group_steps", ctypes.c_uint32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -150,6 +151,7 @@ def _load():
         "zg_stream_get_counter": [P, U32, P],
         "zg_stream_set_counter": [P, U32, U64],
         "zg_batch": [P, P, U32, P, P],
+        "zg_fill_each": [P, P, U32, P],
         "zg_get_tune": [P, ctypes.c_int, P],
         "zg_set_tune": [P, ctypes.c_int, P],
         "zg_autotune": [P, ctypes.c_char_p, U64, ctypes.c_int],
@@ -393,14 +395,24 @@ class Context:
         self._c(lib.zg_batch(self.h, arr, len(requests), first, _stream(hip_stream)), "zg_batch")
         return list(first) if want_first else None
 
+    def zg_fill_each(self, requests, hip_stream=None):
+        """Each request of a list (or an array from zg_batch_prepare) as its
+        own plain launch, in order, from one C loop."""
+        arr = requests if isinstance(requests, ctypes.Array) else self.zg_batch_prepare(requests)
+        self._c(lib.zg_fill_each(self.h, arr, len(requests), _stream(hip_stream)), "zg_fill_each")
+
     # ------------------------------------------------------------- tuning
     def zg_get_tune(self, cls):
+        """(tile, waves_per_block, batch_blocks_per_cu, queue_cap, drain_waves,
+        group_steps) of a tuning class."""
         t = Tune()
         self._c(lib.zg_get_tune(self.h, cls, ctypes.byref(t)), "zg_get_tune")
-        return (t.tile, t.waves_per_block, t.batch_blocks_per_cu, t.queue_cap)
+        return (t.tile, t.waves_per_block, t.batch_blocks_per_cu, t.queue_cap, t.drain_waves,
+                t.group_steps)
 
-    def zg_set_tune(self, cls, tile, waves_per_block, batch_blocks_per_cu=2, queue_cap=0):
-        t = Tune(tile, waves_per_block, batch_blocks_per_cu, queue_cap)
+    def zg_set_tune(self, cls, tile, waves_per_block, batch_blocks_per_cu=2, queue_cap=0,
+                    drain_waves=0, group_steps=4):
+        t = Tune(tile, waves_per_block, batch_blocks_per_cu, queue_cap, drain_waves, group_steps)
         self._c(lib.zg_set_tune(self.h, cls, ctypes.byref(t)), "zg_set_tune")
 
     def zg_autotune(self, cache_path=None, nbytes=0, use_cache=True):

@@ -19,11 +19,11 @@ using namespace zg;
 namespace {
 
 const zg_tune DEFAULT_TUNE[ZG_TUNE_CLASSES] = {
-    {1024, 16, 2, 0},   // FILL_F64: persistent, at most 2 workgroups per CU
-    {4096, 16, 2, 0},   // FILL_F32
-    {2048, 8, 0, 0},    // POLAR
-    {2048, 16, 2, 0},   // MUTATE
-    {2048, 8, 4, 0},    // BATCH (k_batch is bounded to 512 threads)
+    {1024, 16, 2, 0, 0, 4},   // FILL_F64: pooled, persistent, at most 2 workgroups per CU
+    {4096, 16, 2, 0, 0, 4},   // FILL_F32
+    {2048, 8, 0, 0, 0, 4},    // POLAR
+    {2048, 16, 2, 0, 4, 4},   // MUTATE: wave-specialised, 4 drain waves
+    {2048, 8, 4, 0, 0, 4},    // BATCH (k_batch is bounded to 512 threads)
 };
 
 uint32_t chunk_of(uint32_t op) { return op == OP_ZIG32 ? 256u : 128u; }
@@ -87,7 +87,8 @@ zg_status launch_job(zg_ctx *ctx, const Job &J, hipStream_t stream) {
   const zg_tune &t = ctx->tune[tune_class(J.op)];
   uint32_t head = head_of(J.out, J.op, J.n_total);
   hipError_t e = launch_fill(J, ctx->d_tables, ctx->dmax, ctx->d_flags, t.tile, t.waves_per_block,
-                             head, t.queue_cap, t.batch_blocks_per_cu, stream);
+                             head, t.queue_cap, t.batch_blocks_per_cu,
+                             J.op == OP_POLAR ? 0u : t.drain_waves, t.group_steps, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "launch_fill");
   return ZG_OK;
 }
@@ -285,9 +286,11 @@ zg_status zg_fill_sequential(zg_ctx *ctx, double *d_out, uint64_t n, zg_kind kin
   const uint64_t limit = window_of(kind);
   SeqPlan P = seq_plan(n);
   if (first_word >= limit || P.n_pos + 2 > limit - first_word) return ZG_ERANGE;
-  // Plans of more than SEQ_MAX_WG workgroups are refused: the two GPU faults
-  // seen on earlier builds of this path both had more, and their cause is
-  // not shown.  ZG_SEQ_MAX_N keeps plans at 66.
+  // Plans of more than SEQ_MAX_WG workgroups are refused: every run of this
+  // path on the device with more (2^28 variates twice, 10^6 with one window
+  // per chunk once) faulted the GPU, while the CPU build of the same source
+  // at the 2^28 plan is clean and exact; the cause is not shown.
+  // ZG_SEQ_MAX_N keeps plans at 66.
   if (P.n_wg > SEQ_MAX_WG) return ZG_EINVAL;
   if (work_bytes < P.bytes) return ZG_EINVAL;
   {
@@ -466,6 +469,31 @@ zg_status zg_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, uint64_t 
   return st;
 }
 
+zg_status zg_fill_each(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, void *hip_stream) {
+  if (!ctx) return ZG_EINVAL;
+  if (nreq && !reqs) return ZG_EINVAL;
+  // every request is checked before anything is launched
+  for (uint32_t i = 0; i < nreq; ++i) {
+    const zg_request &r = reqs[i];
+    if (r.handle != ZG_NO_HANDLE || (r.op != ZG_OP_FILL && r.op != ZG_OP_MUTATE)) return ZG_EINVAL;
+    if (r.op == ZG_OP_MUTATE && (r.dtype != ZG_F64 || r.method != ZG_ZIGGURAT)) return ZG_EINVAL;
+    uint32_t op;
+    zg_status st = check_gen(r.out, r.n, (zg_dtype)r.dtype, (zg_method)r.method, (zg_kind)r.kind,
+                             r.stream, 1, r.first_index, r.n, &op);
+    if (st != ZG_OK) return st;
+  }
+  for (uint32_t i = 0; i < nreq; ++i) {
+    const zg_request &r = reqs[i];
+    zg_status st = r.op == ZG_OP_MUTATE
+                       ? zg_mutate(ctx, (double *)r.out, r.n, r.sigma, (zg_kind)r.kind, r.seed,
+                                   r.stream, r.first_index, hip_stream)
+                       : zg_fill(ctx, r.out, r.n, (zg_dtype)r.dtype, (zg_method)r.method,
+                                 (zg_kind)r.kind, r.seed, r.stream, r.first_index, hip_stream);
+    if (st != ZG_OK) return st;
+  }
+  return ZG_OK;
+}
+
 // ---------------------------------------------------------------- tuning
 
 zg_status zg_get_tune(const zg_ctx *ctx, int cls, zg_tune *out) {
@@ -484,6 +512,9 @@ zg_status zg_set_tune(zg_ctx *ctx, int cls, const zg_tune *in) {
     return ZG_EINVAL;
   if (cls == ZG_TUNE_BATCH && in->tile % 256) return ZG_EINVAL;
   if (in->queue_cap > 2048) return ZG_EINVAL;
+  if (in->drain_waves > 8) return ZG_EINVAL;
+  if (in->group_steps != 1 && in->group_steps != 2 && in->group_steps != 4 && in->group_steps != 8)
+    return ZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->tune[cls] = *in;
   if (cls == ZG_TUNE_BATCH)

@@ -170,9 +170,13 @@ struct SeqJob {
 // Host entry points of the device code (zg_kernels.hip).
 // resident: 0 = one workgroup per tile; k > 0 = a persistent grid of at most
 // k workgroups per CU (capped by occupancy) looping over the tiles.
+// n_drain > 0 (ziggurat ops): the wave-specialised kernel, one 16-wave
+// workgroup per CU of which n_drain waves resolve the slow elements (tile,
+// waves, qcap and resident do not apply).  gsteps: 256-element steps a wave
+// streams between queue appends (1..8).
 hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
                        uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
-                       uint32_t resident, hipStream_t stream);
+                       uint32_t resident, uint32_t n_drain, uint32_t gsteps, hipStream_t stream);
 hipError_t launch_words(uint64_t *out, uint64_t n, const DevTables *T, uint32_t kind,
                         uint64_t seed, uint32_t s, uint32_t d, uint64_t first, hipStream_t stream);
 hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, uint8_t *cls,

@@ -247,13 +247,6 @@ DEV void split(const Job &J, uint64_t e, uint32_t &s, uint64_t &v) {
 
 DEV void raise_flag(uint32_t *flags, uint32_t bit) { atomicOr(flags, bit); }
 
-// Sign from bit 24 of the word's high dword, applied to the double's high dword.
-// The empty asm keeps the compiler from re-deriving that bit from the last
-// multiply of the hash (it would spend three extra multiplies on it).
-DEV double flip_hi(double x, uint32_t whi) {
-  return __hiloint2double(__double2hiint(x) ^ (int)((whi << 7) & 0x80000000u), __double2loint(x));
-}
-
 // ------------------------------------------------------------ polar path
 //
 // Each wave owns an LDS queue of 32-bit entries (element offset from the
@@ -369,13 +362,13 @@ DEV LaneConst lane_constants(const DevTables *T) {
 // ------------------------------------------------------------- tile work
 
 // FP64 fast path of one element: returns the signed candidate and whether the
-// integer test accepted it.
+// integer test accepted it (tab: the signed table, indexed by the top byte).
 DEV double fast64(const Fast64 *tab, uint64_t W, bool &fast) {
   const uint32_t whi = (uint32_t)(W >> 32), wlo = (uint32_t)W;
-  const Fast64 f = tab[whi >> 25];
+  const Fast64 f = tab[whi >> 24];
   const uint32_t jh = j_hi(whi), jl = j_lo(whi, wlo);
   fast = (((uint64_t)jh << 32) | jl) < f.k;
-  return flip_hi(to_f64(jh, jl) * f.w, whi);
+  return to_f64(jh, jl) * f.w;
 }
 
 // One polar step: a pair per lane (2 elements).
@@ -483,13 +476,18 @@ DEV void polar_tile(const Job &J, const PolarCtx &C, const LaneConst &LC, uint32
 // resolved at once by its own lane, which stored its placeholder.
 
 constexpr uint32_t BSTEP = 256;    // elements per wave step
-constexpr uint32_t BGROUP = 4;     // steps per queue flush
+constexpr uint32_t BGROUP = 4;     // steps per queue flush of the batch kernels (plain
+                                   // fills take it from their launch shape, 1..8)
 constexpr uint32_t BQ = 2048;      // block queue capacity (entries)
 
-// Tables of the fast and slow paths, in LDS.
+// Tables of the fast and slow paths, in LDS.  The fast-path tables are
+// indexed by the word's top byte, layer and sign: entry 2i + s holds k[i] and
+// the width w[i] with the sign s applied (fl(j (-w)) = -fl(j w) exactly, -0.0
+// for j = 0), so the fast path needs no sign step; the slow paths read entry
+// 2i and apply the sign themselves.
 struct LdsTabs {
-  Fast64 f64[ZG_LAYERS];
-  Fast32 f32[ZG_LAYERS];
+  Fast64 f64[2 * ZG_LAYERS];
+  Fast32 f32[2 * ZG_LAYERS];
   double2 yd[ZG_LAYERS];     // (y[i-1], dy[i]) of the wedge test, i >= 1
   double w24d[ZG_LAYERS];    // FP32 mode: w24 as a double
 };
@@ -513,10 +511,14 @@ template <int OP>
 DEV void load_tabs(const DevTables *T, LdsTabs &L) {
   for (uint32_t i = threadIdx.x; i < ZG_LAYERS; i += blockDim.x) {
     if (OP == OP_ZIG32) {
-      L.f32[i] = T->fast32[i];
+      const Fast32 f = T->fast32[i];
+      L.f32[2 * i] = f;
+      L.f32[2 * i + 1] = {f.k, -f.w};
       L.w24d[i] = T->w24d[i];
     } else {
-      L.f64[i] = T->fast64[i];
+      const Fast64 f = T->fast64[i];
+      L.f64[2 * i] = f;
+      L.f64[2 * i + 1] = {f.k, -f.w};
     }
     L.yd[i] = make_double2(i ? T->y[i - 1] : 0.0, T->dy[i]);
   }
@@ -543,7 +545,7 @@ DEV double resolve(const Job &J, const LdsTabs &L, const DevTables *T, double r,
       i = u >> 25;
       neg = (u >> 24) & 1;
       const uint32_t j = u & 0xFFFFFFu;
-      const Fast32 f = L.f32[i];
+      const Fast32 f = L.f32[2 * i];
       if (j < f.k) {
         const float xf = (float)j * f.w;
         z = (double)(neg ? -xf : xf);
@@ -556,7 +558,7 @@ DEV double resolve(const Job &J, const LdsTabs &L, const DevTables *T, double r,
       neg = (uint32_t)(W >> 56) & 1;
       const uint32_t jh = j_hi((uint32_t)(W >> 32)), jl = j_lo((uint32_t)(W >> 32), (uint32_t)W);
       const uint64_t j = ((uint64_t)jh << 32) | jl;
-      const Fast64 f = L.f64[i];
+      const Fast64 f = L.f64[2 * i];
       x = to_f64(jh, jl) * f.w;
       if (j < f.k) {
         z = neg ? -x : x;
@@ -681,11 +683,10 @@ DEV uint32_t step_regs(const Job &J, const Fast64 *f64t, const Fast32 *f32t, con
     const uint64_t e0 = ec + 4ull * lane;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const Fast32 f = f32t[uw[t] >> 25];
+      const Fast32 f = f32t[uw[t] >> 24];
       const uint32_t j = uw[t] & 0xFFFFFFu;
       const bool ok = FULL || e0 + t < e_end;
-      const float v = (float)j * f.w;
-      xf[t] = __int_as_float(__float_as_int(v) ^ (int)((uw[t] << 7) & 0x80000000u));
+      xf[t] = (float)j * f.w;
       b4 |= ((ok && !(j < f.k)) ? 1u : 0u) << t;
     }
   }
@@ -737,10 +738,9 @@ DEV uint32_t step_general(const Job &J, const Fast64 *f64t, const Fast32 *f32t,
       bool fast;
       if (OP == OP_ZIG32) {
         const uint32_t u = word32<KIND>(T, J.seed, s, v, 0);
-        const Fast32 f = f32t[u >> 25];
+        const Fast32 f = f32t[u >> 24];
         const uint32_t j = u & 0xFFFFFFu;
-        const float xv = (float)j * f.w;
-        xf[t] = __int_as_float(__float_as_int(xv) ^ (int)((u << 7) & 0x80000000u));
+        xf[t] = (float)j * f.w;
         fast = j < f.k;
       } else {
         x[t] = fast64(f64t, wordk<KIND>(T, J.seed, s, v, 0), fast);
@@ -794,7 +794,7 @@ DEV bool attempt_at(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t
     i = u >> 25;
     neg = (u >> 24) & 1;
     const uint32_t j = u & 0xFFFFFFu;
-    const Fast32 f = L.f32[i];
+    const Fast32 f = L.f32[2 * i];
     const float xf = (float)j * f.w;
     z = (double)(neg ? -xf : xf);
     x = (double)j * L.w24d[i];
@@ -804,7 +804,7 @@ DEV bool attempt_at(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t
     i = (uint32_t)(W >> 57);
     neg = (uint32_t)(W >> 56) & 1;
     const uint32_t jh = j_hi((uint32_t)(W >> 32)), jl = j_lo((uint32_t)(W >> 32), (uint32_t)W);
-    const Fast64 f = L.f64[i];
+    const Fast64 f = L.f64[2 * i];
     x = to_f64(jh, jl) * f.w;
     z = neg ? -x : x;
     return (((uint64_t)jh << 32) | jl) < f.k;
@@ -817,15 +817,18 @@ DEV bool attempt_at(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t
 // goes to the retry queue (capacity rqc <= RQ), where full rounds of 64
 // finish such variates together; with the retry queue full the lane
 // finishes it itself.  The steps, draws and arithmetic are those of resolve.
+// The first drain step of variate v of stream s whose attempt 0 failed the
+// fast test: that attempt's wedge test and, on rejection, the fast test of
+// attempt 2.  Returns whether that decided the variate (value z); otherwise
+// d is the draw to resume from (0 for a base-strip attempt, 2 after a wedge
+// rejection).  The steps, draws and arithmetic are those of resolve.
 template <int OP, int KIND>
-DEV void drain_first(const Job &J, BlockLds &L, const DevTables *T, double r, uint32_t dmax,
-                     uint32_t rqc, uint64_t e, bool &budget) {
-  uint32_t s;
-  uint64_t v;
-  split(J, e, s, v);
-  uint32_t i, neg, d = 0;
-  double x, z;
-  bool done = attempt_at<OP, KIND>(J, L.t, T, s, v, 0, i, neg, x, z);
+DEV bool first_step(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t dmax, uint32_t s,
+                    uint64_t v, double &z, uint32_t &d, bool &budget) {
+  uint32_t i, neg;
+  double x;
+  d = 0;
+  bool done = attempt_at<OP, KIND>(J, L, T, s, v, 0, i, neg, x, z);
   if (d >= dmax) {
     budget = true;
     z = nan64();
@@ -837,7 +840,7 @@ DEV void drain_first(const Job &J, BlockLds &L, const DevTables *T, double r, ui
       done = true;
     } else {
       const double u = u53(wordk<KIND>(T, J.seed, s, v, d + 1));
-      const double2 yd = L.t.yd[i];
+      const double2 yd = L.yd[i];
       if (yd.x + u * yd.y < exp(-0.5 * (x * x))) {
         z = neg ? -x : x;
         done = true;
@@ -848,11 +851,23 @@ DEV void drain_first(const Job &J, BlockLds &L, const DevTables *T, double r, ui
           z = nan64();
           done = true;
         } else {
-          done = attempt_at<OP, KIND>(J, L.t, T, s, v, d, i, neg, x, z);
+          done = attempt_at<OP, KIND>(J, L, T, s, v, d, i, neg, x, z);
         }
       }
     }
   }
+  return done;
+}
+
+template <int OP, int KIND>
+DEV void drain_first(const Job &J, BlockLds &L, const DevTables *T, double r, uint32_t dmax,
+                     uint32_t rqc, uint64_t e, bool &budget) {
+  uint32_t s;
+  uint64_t v;
+  split(J, e, s, v);
+  uint32_t d;
+  double z;
+  const bool done = first_step<OP, KIND>(J, L.t, T, dmax, s, v, z, d, budget);
   if (!done) {
     const uint32_t p = atomicAdd(&L.rcnt, 1u);
     if (p < rqc) {
@@ -894,7 +909,7 @@ DEV void retry_all(const Job &J, BlockLds &L, const DevTables *T, double r, uint
 }
 
 // The streaming pass over a workgroup tile [b0, b1): the waves take groups
-// of BGROUP steps (1024 elements) in turn from a shared counter, so that
+// of gsteps steps (1..8; 256 elements each) in turn from a shared counter, so that
 // they all run out of work together.  Per step: fast path and stores; per
 // group, each lane with slow elements appends them to the workgroup queue
 // (one LDS atomic per such lane; queue order is immaterial, every result is
@@ -902,8 +917,9 @@ DEV void retry_all(const Job &J, BlockLds &L, const DevTables *T, double r, uint
 // by their own lane at once, after its own store of the same address.
 template <int OP, int KIND>
 DEV void tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneConst &LC,
-                   uint64_t b0, uint64_t b1, uint32_t qcap, uint32_t dmax, uint32_t *flags) {
-  constexpr uint32_t GE = BGROUP * BSTEP;
+                   uint64_t b0, uint64_t b1, uint32_t qcap, uint32_t dmax, uint32_t *flags,
+                   uint32_t gsteps) {
+  const uint32_t GE = gsteps * BSTEP;
   const uint32_t lane = lane_id();
   const bool multi = J.n_streams != 1;
   for (;;) {
@@ -981,7 +997,8 @@ DEV void tile_pass(const Job &J, BlockLds &L, const DevTables *T, const LaneCons
 template <int OP, int KIND>
 DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
                    const LaneConst &LC, double r, uint32_t dmax, uint32_t *flags, uint64_t b0,
-                   uint64_t b1, uint32_t head, uint32_t qcap, bool carry, bool &budget) {
+                   uint64_t b1, uint32_t head, uint32_t qcap, bool carry, bool &budget,
+                   uint32_t gsteps) {
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wave = uni(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
@@ -1000,7 +1017,7 @@ DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
   __syncthreads();
   if (wave * 64 < uni(L.rtake))
     retry_round<OP, KIND>(J, L, T, r, dmax, uni(L.rbeg) + wave * 64, 64, budget);
-  tile_pass<OP, KIND>(J, L, T, LC, b0, b1, qcap, dmax, flags);
+  tile_pass<OP, KIND>(J, L, T, LC, b0, b1, qcap, dmax, flags, gsteps);
   __syncthreads();   // placeholders before patches; the queue is complete
   const uint32_t n = uni(L.cnt < qcap ? L.cnt : qcap);
   for (uint32_t cb = wave * 64; cb < n; cb += nw * 64) {
@@ -1026,7 +1043,8 @@ DEV void zig_block(const Job &J, BlockLds &L, const DevTables *__restrict__ T,
 template <int OP, int KIND>
 __global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict__ T,
                                               uint32_t dmax, uint32_t *flags, uint32_t tile,
-                                              uint32_t head, uint32_t qcap, uint64_t ntiles) {
+                                              uint32_t head, uint32_t qcap, uint64_t ntiles,
+                                              uint32_t gsteps) {
   __shared__ BlockLds L;
   load_tabs<OP>(T, L.t);
   const double r = T->r;
@@ -1038,13 +1056,264 @@ __global__ __launch_bounds__(1024) void k_zig(Job J, const DevTables *__restrict
     const uint64_t b0 = uni64(t * bt + head);
     const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
     zig_block<OP, KIND>(J, L, T, LC, r, dmax, flags, b0, b1, t == 0 ? head : 0u, qcap, true,
-                        budget);
+                        budget, gsteps);
     __syncthreads();   // the next tile resets the queue
   }
   __syncthreads();
   retry_all<OP, KIND>(J, L, T, r, dmax, qcap < RQ ? qcap : RQ, budget);
   if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane_id() == 0)
     raise_flag(flags, ZG_FLAG_BUDGET);
+}
+
+// ------------------------------------------- wave-specialised ziggurat fill
+//
+// The same values as k_zig, with the slow path taken off the streaming
+// waves.  Workgroup w owns one contiguous range of the job.  Its first S
+// waves stream the range in groups of 4 steps (1024 elements) taken from a
+// shared counter: fast path, 128-bit stores with a placeholder where an
+// element failed the fast test, and each such element published in an LDS
+// ring right after its store.  The other waves (one per SIMD) take the
+// ring's entries in rounds of 64, one per lane, resolve each variate in full
+// (resolve: every attempt from draw 0) and store it over its placeholder.
+// No streaming wave waits at a barrier, and a patch follows its placeholder
+// closely, while the line is still in L2.  The ring entry is published after
+// a workgroup-scope release and read before a workgroup-scope acquire, so
+// each patch is ordered after its placeholder.
+//
+// Ring protocol: a writer reserves slots with an atomic on `tail` and waits
+// until its slot is empty (0) before writing element + 1 into it; a drain
+// wave claims [head, head + m) with a compare-and-swap on `head`, waits until
+// each claimed slot is written, reads it and empties it.  The oldest
+// unconsumed slot always has its writer able to proceed (its slot's previous
+// occupant is older, hence consumed), so the ring never deadlocks.  The
+// drain waves leave once every streaming wave has finished and the ring is
+// empty; the elements before the first aligned one are resolved after a
+// final barrier.
+
+constexpr uint32_t WS_RING = 2048;   // ring slots (a power of two)
+
+constexpr uint32_t WS_MAX_DRAIN = 8;
+constexpr uint32_t WS_RQ = 128;     // retry entries per drain wave
+
+struct WsLds {
+  LdsTabs t;
+  uint32_t next;    // next group of the workgroup's range to stream
+  uint32_t tail;    // ring slots reserved
+  uint32_t head;    // ring slots claimed by drain waves
+  uint32_t done;    // streaming waves that have finished
+  uint64_t ring[WS_RING];   // element + 1; 0 = empty
+  uint64_t rq[WS_MAX_DRAIN][WS_RQ];   // each drain wave's undecided variates (element | draw << ENT_D)
+};
+
+DEV uint32_t lds_load(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Streaming role: the workgroup's groups in turn (group c of workgroup w is
+// group c * gridDim.x + w of the body that starts at b0, so the workgroups
+// write neighbouring groups at any time), each lane's slow elements published
+// in the ring after the group's stores.
+template <int OP, int KIND>
+DEV void ws_stream(const Job &J, WsLds &L, const DevTables *T, const LaneConst &LC, uint64_t b0,
+                   uint64_t b1, uint32_t gsteps) {
+  const uint32_t lane = lane_id();
+  const uint32_t GE = gsteps * BSTEP;
+  const bool multi = J.n_streams != 1;
+  for (;;) {
+    uint32_t g = 0;
+    if (lane == 0) g = atomicAdd(&L.next, 1u);
+    const uint64_t gs = b0 + ((uint64_t)uni(g) * gridDim.x + blockIdx.x) * GE;
+    if (gs >= b1) break;
+    const uint64_t ge = gs + GE < b1 ? gs + GE : b1;
+    uint32_t s = J.s0;
+    uint64_t rr = gs;
+    if (multi) {
+      uint64_t v;
+      split(J, gs, s, v);
+      s = uni(s);
+      rr = uni64(v - J.first);
+    }
+    uint32_t bits = 0, sub = 0;
+    uint64_t Sc = 0;
+    bool have = false;
+    for (uint64_t ec = gs; ec < ge; ec += BSTEP, ++sub) {
+      double x[4];
+      float xf[4];
+      uint32_t b4;
+      const bool full = ec + BSTEP <= ge;
+      if (!multi || rr + BSTEP <= J.n_per) {
+        const uint64_t vc = J.first + rr;
+        if (KIND == ZG_JAVA_LCG48 && !have) {
+          Sc = lcg_jump(&T->lcg, lcg_state0(J.seed), 2 * lcg_index(s, vc, 0) + 1);
+          have = true;
+        }
+        if (full)
+          b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
+        else
+          b4 = step_regs<OP, KIND, false>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
+        if (KIND == ZG_JAVA_LCG48) Sc = aff(T->lcg.jump[1][2], Sc);
+      } else {
+        b4 = step_general<OP, KIND>(J, L.t.f64, L.t.f32, T, ec, ge, x, xf);
+        have = false;
+      }
+      if (full)
+        step_store<OP, true>(J, ec, ge, x, xf);
+      else
+        step_store<OP, false>(J, ec, ge, x, xf);
+      bits |= b4 << (4 * sub);
+      rr += BSTEP;
+      if (multi)
+        while (rr >= J.n_per) {
+          rr -= J.n_per;
+          ++s;
+          have = false;
+        }
+    }
+    if (bits) {
+      // the placeholders before their ring entries
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      uint32_t p = atomicAdd(&L.tail, (uint32_t)__builtin_popcount(bits));
+      do {
+        const uint32_t b = __builtin_ctz(bits);
+        const uint64_t e = gs + (b >> 2) * BSTEP + slot_elem<OP>(0, lane, b & 3);
+        uint64_t *slot = &L.ring[p & (WS_RING - 1)];
+        while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+          __builtin_amdgcn_s_sleep(1);
+        __hip_atomic_store(slot, e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        bits &= bits - 1;
+        ++p;
+      } while (bits);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (lane == 0) atomicAdd(&L.done, 1u);
+}
+
+// A round over the last n (<= 64) entries of a drain wave's retry queue,
+// one per lane, each finished by resolve from its recorded draw.
+template <int OP, int KIND>
+DEV void ws_retry(const Job &J, const LdsTabs &L, const DevTables *T, double r, uint32_t dmax,
+                  const uint64_t *rq, uint32_t base, uint32_t n, bool &budget) {
+  const uint32_t lane = lane_id();
+  if (lane < n) {
+    const uint64_t ent = rq[base + lane];
+    const uint64_t e = ent & ENT_E;
+    uint32_t s;
+    uint64_t v;
+    split(J, e, s, v);
+    patch_store<OP>(J, e, resolve<OP, KIND>(J, L, T, r, dmax, s, v, budget,
+                                            (uint32_t)(ent >> ENT_D)));
+  }
+}
+
+// Drain role: rounds of up to 64 ring entries until every streaming wave has
+// finished and the ring is empty.  While streaming goes on, only full rounds
+// are claimed.  Each entry gets its first drain step; the few it leaves
+// undecided (and the base-strip attempts) go to the wave's own retry queue,
+// which is finished 64 at a time, the rest at the end.
+template <int OP, int KIND>
+DEV void ws_drain(const Job &J, WsLds &L, const DevTables *T, double r, uint32_t dmax,
+                  uint32_t n_stream, uint32_t slot_id, bool &budget) {
+  const uint32_t lane = lane_id();
+  uint64_t *rq = L.rq[slot_id];
+  uint32_t rn = 0;   // wave-uniform
+  for (;;) {
+    const uint32_t fin = uni(lds_load(&L.done));
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint32_t h = uni(lds_load(&L.head));
+    const uint32_t tl = uni(lds_load(&L.tail));
+    const uint32_t avail = tl - h;
+    if (avail == 0 && fin == n_stream) break;
+    if (avail < 64 && fin != n_stream) {
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    const uint32_t m = avail < 64 ? avail : 64;
+    uint32_t got = 0;
+    if (lane == 0) got = atomicCAS(&L.head, h, h + m) == h ? 1u : 0u;
+    if (uni(got) == 0) continue;
+    bool und = false;
+    uint64_t rent = 0;
+    if (lane < m) {
+      uint64_t *slot = &L.ring[(h + lane) & (WS_RING - 1)];
+      uint64_t ent;
+      while ((ent = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) == 0)
+        __builtin_amdgcn_s_sleep(1);
+      __hip_atomic_store(slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      const uint64_t e = ent - 1;
+      uint32_t s;
+      uint64_t v;
+      split(J, e, s, v);
+      double z;
+      uint32_t d;
+      if (first_step<OP, KIND>(J, L.t, T, dmax, s, v, z, d, budget)) {
+        patch_store<OP>(J, e, z);
+      } else {
+        und = true;
+        rent = e | ((uint64_t)d << ENT_D);
+      }
+    }
+    // undecided: to this wave's retry queue (rn < 64 before, so it fits)
+    const uint64_t mk = __builtin_amdgcn_ballot_w64(und);
+    if (mk) {
+      if (und) rq[rn + prefix_below(mk)] = rent;
+      rn = uni(rn + (uint32_t)__popcll(mk));
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (rn >= 64) {
+      rn -= 64;
+      ws_retry<OP, KIND>(J, L.t, T, r, dmax, rq, rn, 64, budget);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  while (rn) {
+    const uint32_t m = rn < 64 ? rn : 64;
+    rn -= m;
+    ws_retry<OP, KIND>(J, L.t, T, r, dmax, rq, rn, m, budget);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Plain fills, wave-specialised: a persistent grid; workgroup w streams the
+// groups w, w + gridDim.x, ... of the body [head, n_total) with its first
+// (waves - n_drain) waves while its last n_drain waves resolve the slow
+// elements.
+template <int OP, int KIND>
+__global__ __launch_bounds__(1024) void k_zigws(Job J, const DevTables *__restrict__ T,
+                                                uint32_t dmax, uint32_t *flags, uint32_t head,
+                                                uint32_t n_drain, uint32_t gsteps) {
+  __shared__ WsLds L;
+  load_tabs<OP>(T, L.t);
+  for (uint32_t i = threadIdx.x; i < WS_RING; i += blockDim.x) L.ring[i] = 0;
+  if (threadIdx.x == 0) {
+    L.next = 0;
+    L.tail = 0;
+    L.head = 0;
+    L.done = 0;
+  }
+  __syncthreads();
+  const double r = T->r;
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t n_stream = nw - n_drain;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const uint32_t lane = lane_id();
+  bool budget = false;
+  if (wave < n_stream) {
+    const LaneConst LC = lane_constants<OP, KIND>(T);
+    ws_stream<OP, KIND>(J, L, T, LC, head, J.n_total, gsteps);
+  } else {
+    ws_drain<OP, KIND>(J, L, T, r, dmax, n_stream, wave - n_stream, budget);
+  }
+  __syncthreads();
+  // the elements before the first aligned one
+  if (blockIdx.x == 0 && wave == 0 && lane < head) {
+    uint32_t se;
+    uint64_t ve;
+    split(J, lane, se, ve);
+    patch_store<OP>(J, lane, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
+  }
+  if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane == 0) raise_flag(flags, ZG_FLAG_BUDGET);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -1181,7 +1450,7 @@ __global__ __launch_bounds__(1024) void k_bzig(DevRequest *R, const BatchHeader 
       const uint64_t b0 = uni64(rq.head + j * bt);
       const uint64_t b1 = uni64(b0 + bt < J.n_total ? b0 + bt : J.n_total);
       zig_block<OP, KIND>(J, L, T, LC, r, dmax, flags, b0, b1, j == 0 ? rq.head : 0u, BQ, false,
-                          budget);
+                          budget, BGROUP);
     }
     __syncthreads();   // the next tile resets the queue
   }
@@ -1315,7 +1584,7 @@ DEV SeqAtt seq_attempt(const LdsTabs &L, const DevTables *T, double r, const Seq
   const uint32_t whi = (uint32_t)(W >> 32), wlo = (uint32_t)W;
   const uint32_t i = whi >> 25;
   const uint32_t neg = (whi >> 24) & 1u;
-  const Fast64 f = L.f64[i];
+  const Fast64 f = L.f64[2 * i];
   const uint32_t jh = j_hi(whi), jl = j_lo(whi, wlo);
   const double x = to_f64(jh, jl) * f.w;
   SeqAtt a;
@@ -1594,9 +1863,26 @@ __global__ __launch_bounds__(64) void k_seq_finish(SeqJob J, const DevTables *__
 template <int OP, int KIND>
 static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
                                  uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
-                                 uint32_t resident, hipStream_t stream) {
+                                 uint32_t resident, uint32_t n_drain, uint32_t gsteps,
+                                 hipStream_t stream) {
   uint64_t body = J.n_total > head ? J.n_total - head : 0;
+  if (gsteps < 1 || gsteps > 8) gsteps = BGROUP;
   if constexpr (OP != OP_POLAR) {
+    if (n_drain > 0) {
+      // wave-specialised: one 16-wave workgroup per CU, each owning an equal
+      // range of whole groups
+      int dev = 0, cus = 256;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      const uint32_t nw = 16;
+      if (n_drain > WS_MAX_DRAIN) n_drain = WS_MAX_DRAIN;
+      const uint64_t ge = (uint64_t)gsteps * BSTEP;
+      const uint64_t groups = (body + ge - 1) / ge;
+      uint64_t blocks = groups < (uint64_t)cus ? (groups ? groups : 1) : (uint64_t)cus;
+      hipLaunchKernelGGL((k_zigws<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * nw), 0, stream, J,
+                         T, dmax, flags, head, n_drain, gsteps);
+      return hipGetLastError();
+    }
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1621,7 +1907,7 @@ static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax
     }
     const uint32_t qc = qcap == 0 || qcap > BQ ? BQ : qcap;
     hipLaunchKernelGGL((k_zig<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * waves), 0, stream, J,
-                       T, dmax, flags, tile, head, qc, ntiles);
+                       T, dmax, flags, tile, head, qc, ntiles, gsteps);
   } else {
     (void)resident;
     (void)qcap;
@@ -1639,26 +1925,32 @@ static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax
 template <int OP>
 static hipError_t launch_kind(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
                               uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
-                              uint32_t resident, hipStream_t stream) {
+                              uint32_t resident, uint32_t n_drain, uint32_t gsteps,
+                              hipStream_t stream) {
   if (J.kind == ZG_JAVA_LCG48)
     return launch_fill_op<OP, ZG_JAVA_LCG48>(J, T, dmax, flags, tile, waves, head, qcap, resident,
-                                             stream);
+                                             n_drain, gsteps, stream);
   return launch_fill_op<OP, ZG_SPLITMIX64>(J, T, dmax, flags, tile, waves, head, qcap, resident,
-                                           stream);
+                                           n_drain, gsteps, stream);
 }
 
 hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
                        uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
-                       uint32_t resident, hipStream_t stream) {
+                       uint32_t resident, uint32_t n_drain, uint32_t gsteps,
+                       hipStream_t stream) {
   switch (J.op) {
     case OP_ZIG64:
-      return launch_kind<OP_ZIG64>(J, T, dmax, flags, tile, waves, head, qcap, resident, stream);
+      return launch_kind<OP_ZIG64>(J, T, dmax, flags, tile, waves, head, qcap, resident, n_drain,
+                                   gsteps, stream);
     case OP_ZIG32:
-      return launch_kind<OP_ZIG32>(J, T, dmax, flags, tile, waves, head, qcap, resident, stream);
+      return launch_kind<OP_ZIG32>(J, T, dmax, flags, tile, waves, head, qcap, resident, n_drain,
+                                   gsteps, stream);
     case OP_POLAR:
-      return launch_kind<OP_POLAR>(J, T, dmax, flags, tile, waves, head, qcap, resident, stream);
+      return launch_kind<OP_POLAR>(J, T, dmax, flags, tile, waves, head, qcap, resident, n_drain,
+                                   gsteps, stream);
     default:
-      return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, qcap, resident, stream);
+      return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, qcap, resident, n_drain,
+                                    gsteps, stream);
   }
 }
 

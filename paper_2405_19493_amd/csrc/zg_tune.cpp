@@ -1,8 +1,12 @@
-// Launch-shape autotuner: for each kernel class, times a small grid of
-// (tile, waves per block[, persistent blocks per CU]) on a scratch buffer and
-// keeps the fastest.  The output bits do not depend on the shape (variates are
-// index-keyed), so tuning never changes results.  Results are cached in a
-// small JSON file keyed by the device architecture.
+// Launch-shape autotuner: for each kernel class, times a small grid of shapes
+// on a scratch buffer and keeps the fastest: for the plain ziggurat fills the
+// block-pooled kernel at (tile, waves per block, persistent blocks per CU,
+// steps per group) and the wave-specialised kernel at (drain waves, steps per
+// group); for the polar kernel (tile, waves); for the batch kernels (tile,
+// waves, persistent blocks per CU).  The output bits do not depend on the
+// shape (variates are index-keyed), so tuning never changes results.  Results
+// are cached in a small JSON file keyed by the device architecture and the
+// HIP runtime version.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,10 +38,11 @@ bool read_cache(const char *path, const std::string &arch, zg_tune *out) {
     std::string ck = std::string("\"") + CLASS_NAME[c] + "\"";
     size_t p = text.find(ck, pos);
     if (p == std::string::npos) return false;
-    unsigned a, b, d;
-    if (std::sscanf(text.c_str() + p + ck.size(), " : [ %u , %u , %u ]", &a, &b, &d) != 3)
+    unsigned a, b, d, w, g;
+    if (std::sscanf(text.c_str() + p + ck.size(), " : [ %u , %u , %u , %u , %u ]", &a, &b, &d,
+                    &w, &g) != 5)
       return false;
-    out[c] = {a, b, d, 0};
+    out[c] = {a, b, d, 0, w, g};
   }
   return true;
 }
@@ -47,8 +52,9 @@ bool write_cache(const char *path, const std::string &arch, const zg_tune *t) {
   if (!f) return false;
   std::fprintf(f, "{\n  \"%s\": {\n", arch.c_str());
   for (int c = 0; c < ZG_TUNE_CLASSES; ++c)
-    std::fprintf(f, "    \"%s\": [%u, %u, %u]%s\n", CLASS_NAME[c], t[c].tile, t[c].waves_per_block,
-                 t[c].batch_blocks_per_cu, c + 1 < ZG_TUNE_CLASSES ? "," : "");
+    std::fprintf(f, "    \"%s\": [%u, %u, %u, %u, %u]%s\n", CLASS_NAME[c], t[c].tile,
+                 t[c].waves_per_block, t[c].batch_blocks_per_cu, t[c].drain_waves,
+                 t[c].group_steps, c + 1 < ZG_TUNE_CLASSES ? "," : "");
   std::fprintf(f, "  }\n}\n");
   std::fclose(f);
   return true;
@@ -76,7 +82,11 @@ float time_ms(F fn, hipStream_t s, hipEvent_t a, hipEvent_t b, int reps) {
 extern "C" zg_status zg_autotune(zg_ctx *ctx, const char *cache_path, uint64_t bytes,
                                  int use_cache) {
   if (!ctx) return ZG_EINVAL;
+  // cache key: the architecture and the HIP runtime (a new runtime may favour
+  // other shapes)
   std::string arch = ctx->arch.empty() ? std::string("unknown") : ctx->arch;
+  int rt = 0;
+  if (hipRuntimeGetVersion(&rt) == hipSuccess) arch += " hip " + std::to_string(rt);
   if (use_cache && cache_path) {
     zg_tune t[ZG_TUNE_CLASSES];
     if (read_cache(cache_path, arch, t)) {
@@ -101,43 +111,49 @@ extern "C" zg_status zg_autotune(zg_ctx *ctx, const char *cache_path, uint64_t b
   if (e == hipSuccess) e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   zg_status st = e == hipSuccess ? ZG_OK : hip_fail(ctx, e, "autotune setup");
-  const uint32_t tiles64[] = {1024, 2048, 4096};
-  const uint32_t waves[] = {8, 16};
-  const uint32_t resident[] = {0, 2};   // one workgroup per tile, or persistent
+  // candidate shapes of the plain fills: block-pooled ones, then
+  // wave-specialised ones (drain waves > 0; tile and waves do not apply)
+  std::vector<zg_tune> cands;
+  for (uint32_t tl : {1024u, 2048u, 4096u})
+    for (uint32_t w : {8u, 16u})
+      for (uint32_t res : {0u, 2u})
+        for (uint32_t gs : {2u, 4u}) cands.push_back({tl, w, res, 0, 0, gs});
+  for (uint32_t dw : {3u, 4u, 6u, 8u})
+    for (uint32_t gs : {2u, 4u, 8u}) cands.push_back({1024, 16, 2, 0, dw, gs});
   for (int c = 0; c < ZG_TUNE_CLASSES - 1 && st == ZG_OK; ++c) {
     zg_tune best = ctx->tune[c];
     float best_ms = 1e30f;
-    for (uint32_t tl : tiles64)
-      for (uint32_t w : waves)
-        for (uint32_t res : resident) {
-        if (c == ZG_TUNE_POLAR && res) continue;   // the polar kernel is never persistent
-        zg_tune cand = {c == ZG_TUNE_FILL_F32 ? 2 * tl : tl, w, res, 0};
-        st = zg_set_tune(ctx, c, &cand);
-        if (st != ZG_OK) break;
-        auto run = [&]() {
-          uint64_t n8 = bytes / 8, n4 = bytes / 4;
-          switch (c) {
-            case ZG_TUNE_FILL_F64:
-              zg_fill(ctx, buf, n8, ZG_F64, ZG_ZIGGURAT, ZG_SPLITMIX64, 1, 0, 0, s);
-              break;
-            case ZG_TUNE_FILL_F32:
-              zg_fill(ctx, buf, n4, ZG_F32, ZG_ZIGGURAT, ZG_SPLITMIX64, 1, 0, 0, s);
-              break;
-            case ZG_TUNE_POLAR:
-              zg_fill(ctx, buf, n8, ZG_F64, ZG_POLAR, ZG_SPLITMIX64, 1, 0, 0, s);
-              break;
-            default:
-              zg_mutate(ctx, (double *)buf, n8 / 2, 0.0, ZG_SPLITMIX64, 1, 0, 0, s);
-              break;
-          }
-        };
-        if (c == ZG_TUNE_MUTATE) (void)hipMemsetAsync(buf, 0, bytes, s);
-        float ms = time_ms(run, s, a, b, 5);
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = cand;
+    for (const zg_tune &base : cands) {
+      zg_tune cand = base;
+      if (c == ZG_TUNE_POLAR && (cand.batch_blocks_per_cu || cand.drain_waves || cand.group_steps != 4))
+        continue;   // the polar kernel is never persistent and has no groups
+      if (c == ZG_TUNE_FILL_F32) cand.tile *= 2;
+      st = zg_set_tune(ctx, c, &cand);
+      if (st != ZG_OK) break;
+      auto run = [&]() {
+        uint64_t n8 = bytes / 8, n4 = bytes / 4;
+        switch (c) {
+          case ZG_TUNE_FILL_F64:
+            zg_fill(ctx, buf, n8, ZG_F64, ZG_ZIGGURAT, ZG_SPLITMIX64, 1, 0, 0, s);
+            break;
+          case ZG_TUNE_FILL_F32:
+            zg_fill(ctx, buf, n4, ZG_F32, ZG_ZIGGURAT, ZG_SPLITMIX64, 1, 0, 0, s);
+            break;
+          case ZG_TUNE_POLAR:
+            zg_fill(ctx, buf, n8, ZG_F64, ZG_POLAR, ZG_SPLITMIX64, 1, 0, 0, s);
+            break;
+          default:
+            zg_mutate(ctx, (double *)buf, n8 / 2, 0.0, ZG_SPLITMIX64, 1, 0, 0, s);
+            break;
         }
+      };
+      if (c == ZG_TUNE_MUTATE) (void)hipMemsetAsync(buf, 0, bytes, s);
+      float ms = time_ms(run, s, a, b, 5);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand;
       }
+    }
     if (st == ZG_OK) st = zg_set_tune(ctx, c, &best);
   }
   // batch: a synthetic uneven batch of fills over the scratch buffer
@@ -168,7 +184,7 @@ extern "C" zg_status zg_autotune(zg_ctx *ctx, const char *cache_path, uint64_t b
     for (uint32_t tl : btiles)
       for (uint32_t w : {4u, 8u})
         for (uint32_t k : bpc) {
-          zg_tune cand = {tl, w, k, 0};
+          zg_tune cand = {tl, w, k, 0, 0, 4};
           st = zg_set_tune(ctx, ZG_TUNE_BATCH, &cand);
           if (st != ZG_OK) break;
           auto run = [&]() { zg_batch(ctx, reqs.data(), (uint32_t)reqs.size(), nullptr, s); };

@@ -1,11 +1,20 @@
-// The sequential-consumption passes (k_seq_maps, k_seq_scan, k_seq_write,
-// k_seq_finish) built from the kernel source for the host, with the shim in
-// tests/host/shim, and run through launch_seq:
-//   seq_emu N KIND SEED STREAM FIRST OUTFILE
-// writes the position after the last word read, then the N values.  Built
-// with AddressSanitizer, so that any access outside its buffer stops it.
+// The device source of libzg built for the host, with the shim in
+// tests/host/shim, and run through its own launch functions.  Built with
+// AddressSanitizer, so that any access outside its buffer stops it.
+//   kernel_emu N KIND SEED STREAM FIRST OUTFILE
+//     the sequential-consumption passes (launch_seq): writes the position
+//     after the last word read, then the N values;
+//   kernel_emu scan N_WG SEED
+//     the scan pass alone over synthetic maps (see scan_only);
+//   kernel_emu fill OP KIND SEED S0 NSTREAMS NPER FIRST HEAD NDRAIN GSTEPS OUTFILE [INFILE]
+//     a plain fill (launch_fill) of NSTREAMS x NPER elements, OP 0 FP64,
+//     1 FP32, 3 mutation (sigma 0.1, the initial doubles read from INFILE),
+//     with the output HEAD elements past a 16-byte boundary, by the pooled
+//     kernel (NDRAIN 0) or the wave-specialised one with NDRAIN drain waves,
+//     GSTEPS steps per group; writes the values.
 #include "hip/hip_runtime.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -74,7 +83,7 @@ alignas(16) unsigned char s_polar[1 << 17];
 
 using namespace zg;
 
-// seq_emu scan N_WG SEED: the scan pass alone over N_WG synthetic workgroup
+// kernel_emu scan N_WG SEED: the scan pass alone over N_WG synthetic workgroup
 // maps (random counts, random exits), against the maps composed in order one
 // at a time.  Prints "scan ok" or the first difference.
 static int scan_only(uint32_t n_wg, uint64_t seed) {
@@ -124,17 +133,9 @@ static int scan_only(uint32_t n_wg, uint64_t seed) {
   return bad;
 }
 
-int main(int argc, char **argv) {
-  if (argc == 4 && std::strcmp(argv[1], "scan") == 0)
-    return scan_only((uint32_t)strtoul(argv[2], 0, 10), strtoull(argv[3], 0, 10));
-  if (argc < 7) return 2;
-  const uint64_t n = strtoull(argv[1], 0, 10);
-  const uint32_t kind = (uint32_t)atoi(argv[2]);
-  const uint64_t seed = strtoull(argv[3], 0, 10);
-  const uint32_t s = (uint32_t)atoi(argv[4]);
-  const uint64_t first = strtoull(argv[5], 0, 10);
+static DevTables *host_tables() {
   zg_table_view tv;
-  if (build_table(&tv) != ZG_OK) return 2;
+  if (build_table(&tv) != ZG_OK) return nullptr;
   DevTables *T = new DevTables();
   std::memset(T, 0, sizeof(*T));
   for (int i = 0; i < ZG_LAYERS; ++i) {
@@ -148,6 +149,70 @@ int main(int argc, char **argv) {
   T->r = tv.r;
   build_lcg_tables(&T->lcg);
   build_log_tables(&T->logt);
+  return T;
+}
+
+static int fill_only(char **a) {
+  const uint32_t op = (uint32_t)atoi(a[0]), kind = (uint32_t)atoi(a[1]);
+  const uint64_t seed = strtoull(a[2], 0, 10);
+  const uint32_t s0 = (uint32_t)atoi(a[3]), ns = (uint32_t)atoi(a[4]);
+  const uint64_t n_per = strtoull(a[5], 0, 10), first = strtoull(a[6], 0, 10);
+  const uint32_t head = (uint32_t)atoi(a[7]), n_drain = (uint32_t)atoi(a[8]);
+  const uint32_t gsteps = (uint32_t)atoi(a[9]);
+  const char *outfile = a[10], *infile = a[11];
+  const uint64_t n = (uint64_t)ns * n_per;
+  const size_t esz = op == OP_ZIG32 ? 4 : 8;
+  const uint32_t per16 = (uint32_t)(16 / esz);
+  if (head >= per16 || n == 0) return 2;
+  DevTables *T = host_tables();
+  if (!T) return 2;
+  // exactly n elements, starting `head` elements before a 16-byte boundary
+  const size_t lead = (per16 - head) % per16;
+  // malloc's blocks are 16-byte aligned here; the exact size lets
+  // AddressSanitizer see any store past the last element
+  char *base = (char *)malloc((n + lead) * esz);
+  if (((uintptr_t)base) % 16) return 5;
+  void *out = base + lead * esz;
+  std::vector<char> keep(n * esz);
+  if (op == OP_MUTATE) {
+    FILE *f = fopen(infile, "rb");
+    if (!f || fread(out, 8, n, f) != n) return 3;
+    fclose(f);
+  }
+  uint32_t *flags = (uint32_t *)calloc(1, sizeof(uint32_t));
+  Job J{out, n_per, n, first, seed, 0.1, 1.0 / (double)n_per, s0, ns, kind, op};
+  const uint32_t h = op == OP_ZIG32 ? (uint32_t)((4 - (((uintptr_t)out >> 2) & 3)) & 3)
+                                    : (uint32_t)(((uintptr_t)out >> 3) & 1);
+  const uint32_t hd = (uint32_t)std::min<uint64_t>(h, n);
+  std::fprintf(stderr, "fill op=%u n=%llu head=%u drain=%u\n", op, (unsigned long long)n, hd,
+               n_drain);
+  if (launch_fill(J, T, ZG_MAX_DRAWS, flags, 1024, 16, hd, 0, 2, n_drain, gsteps, nullptr) !=
+      hipSuccess)
+    return 4;
+  FILE *f = fopen(outfile, "wb");
+  if (!f) return 3;
+  fwrite(out, esz, n, f);
+  fclose(f);
+  std::fprintf(stderr, "flags=%u\n", *flags);
+  free(base);
+  free(flags);
+  delete T;
+  pools.clear();
+  return 0;
+}
+
+int main(int argc, char **argv) {
+  if (argc == 4 && std::strcmp(argv[1], "scan") == 0)
+    return scan_only((uint32_t)strtoul(argv[2], 0, 10), strtoull(argv[3], 0, 10));
+  if (argc >= 13 && std::strcmp(argv[1], "fill") == 0) return fill_only(argv + 2);
+  if (argc < 7) return 2;
+  const uint64_t n = strtoull(argv[1], 0, 10);
+  const uint32_t kind = (uint32_t)atoi(argv[2]);
+  const uint64_t seed = strtoull(argv[3], 0, 10);
+  const uint32_t s = (uint32_t)atoi(argv[4]);
+  const uint64_t first = strtoull(argv[5], 0, 10);
+  DevTables *T = host_tables();
+  if (!T) return 2;
   // the plan of zg_fill_sequential (without its size caps), and a workspace
   // of exactly its size
   const SeqPlan P = seq_plan(n);

@@ -92,7 +92,7 @@ size_t batch_class_lds_bytes(int, uint32_t) { return 0; }
 
 // The plain paths are not part of this harness.
 hipError_t launch_fill(const Job &, const DevTables *, uint32_t, uint32_t *, uint32_t, uint32_t,
-                       uint32_t, uint32_t, uint32_t, uint32_t, hipStream_t) {
+                       uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, hipStream_t) {
   return hipErrorInvalidValue;
 }
 hipError_t launch_words(uint64_t *, uint64_t, const DevTables *, uint32_t, uint64_t, uint32_t,

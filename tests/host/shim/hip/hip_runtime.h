@@ -9,6 +9,7 @@
 #include <barrier>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -43,7 +44,13 @@ inline hipError_t hipGetSymbolAddress(void **p, const void *sym) { *p = const_ca
 #define hipDeviceAttributeMultiprocessorCount 1
 inline hipError_t hipGetLastError() { return 0; }
 inline hipError_t hipGetDevice(int *d) { *d = 0; return 0; }
-inline hipError_t hipDeviceGetAttribute(int *v, int, int) { *v = 256; return 0; }
+// compute units: EMU_CUS from the environment (default 256), so that a test
+// can make persistent grids of few, large workgroups
+inline hipError_t hipDeviceGetAttribute(int *v, int, int) {
+  const char *e = std::getenv("EMU_CUS");
+  *v = e ? std::atoi(e) : 256;
+  return 0;
+}
 inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *o, const void *, int, size_t) { *o = 1; return 0; }
 
 // ---- collectives
@@ -91,8 +98,16 @@ inline uint32_t atomicAdd(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p
 inline int32_t atomicAdd(int32_t *p, int32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline uint32_t atomicOr(uint32_t *p, uint32_t v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
 inline int32_t atomicSub(int32_t *p, int32_t v) { return __atomic_fetch_sub(p, v, __ATOMIC_SEQ_CST); }
+inline uint32_t atomicCAS(uint32_t *p, uint32_t cmp, uint32_t val) {
+  __atomic_compare_exchange_n(p, &cmp, val, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+  return cmp;
+}
 #define __HIP_MEMORY_SCOPE_SYSTEM 0
+#define __HIP_MEMORY_SCOPE_WORKGROUP 1
 #define __hip_atomic_store(p, v, o, s) __atomic_store_n(p, v, __ATOMIC_SEQ_CST)
+#define __hip_atomic_load(p, o, s) __atomic_load_n(p, __ATOMIC_SEQ_CST)
+#define __builtin_amdgcn_fence(o, s) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
 
 inline double __longlong_as_double(long long x) { double d; std::memcpy(&d, &x, 8); return d; }
 inline long long __double_as_longlong(double x) { long long d; std::memcpy(&d, &x, 8); return d; }

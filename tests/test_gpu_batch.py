@@ -95,8 +95,8 @@ def test_batch_equals_plain_calls_and_shapes(ctx, zg):
                     ctx.zg_fill(o, kind=r["kind"], seed=r["seed"], stream=r["stream"], first_index=r["first_index"])
                 assert host(o).tobytes() == want.tobytes(), ("plain", tile, waves)
     finally:
-        for c, (t, w, b, q) in saved.items():
-            ctx.zg_set_tune(c, t, w, b, q)
+        for c, t in saved.items():
+            ctx.zg_set_tune(c, *t)
 
 
 def test_counters_continue_and_checkpoint(ctx, zg):

@@ -216,7 +216,7 @@ def test_queue_overflow_path(ctx, zg, qcap):
             multi = n == 37 * 1000
             outs = []
             for cap in (0, qcap):
-                tile, waves, bpc, _ = saved[cls_t]
+                tile, waves, bpc = saved[cls_t][:3]
                 ctx.zg_set_tune(cls_t, tile, waves, bpc, cap)
                 out = dev_empty(n, tdt, offset)
                 out.fill_(float("nan"))
@@ -239,7 +239,7 @@ def test_queue_overflow_path(ctx, zg, qcap):
         # mutation
         rng = np.random.Generator(np.random.PCG64(6))
         x0 = rng.uniform(-3.0, 3.0, 50001)
-        tile, waves, bpc, _ = saved[zg.ZG_TUNE_MUTATE]
+        tile, waves, bpc = saved[zg.ZG_TUNE_MUTATE][:3]
         ctx.zg_set_tune(zg.ZG_TUNE_MUTATE, tile, waves, bpc, qcap)
         x = dev_empty(x0.size, torch.float64, 1)
         x.copy_(torch.from_numpy(x0))
@@ -254,15 +254,20 @@ def test_queue_overflow_path(ctx, zg, qcap):
 @pytest.mark.parametrize("cls_t,tdt", [(0, torch.float64), (1, torch.float32), (3, torch.float64)])
 def test_launch_shape_never_changes_bits(ctx, zg, cls_t, tdt):
     """One workgroup per tile or a persistent grid, small or large tiles,
-    4 to 16 waves: the same bits (every variate is keyed by its index)."""
+    4 to 16 waves, 1 to 8 steps per group, the block-pooled or the
+    wave-specialised kernel with 1 to 8 drain waves: the same bits (every
+    variate is keyed by its index)."""
     n = 3 * 65536 + 4097
     saved = ctx.zg_get_tune(cls_t)
     rng = np.random.Generator(np.random.PCG64(12))
     x0 = torch.from_numpy(rng.uniform(-1, 1, n)).cuda() if cls_t == 3 else None
     try:
         ref = None
-        for tile, waves, res in [(2048, 16, 2), (256, 4, 0), (512, 8, 1), (4096, 16, 0), (1024, 16, 4)]:
-            ctx.zg_set_tune(cls_t, tile, waves, res)
+        for tile, waves, res, dw, gs in [(2048, 16, 2, 0, 4), (256, 4, 0, 0, 1), (512, 8, 1, 0, 8),
+                                         (4096, 16, 0, 0, 2), (1024, 16, 4, 0, 4),
+                                         (1024, 16, 2, 1, 4), (1024, 16, 2, 4, 2),
+                                         (1024, 16, 2, 8, 8)]:
+            ctx.zg_set_tune(cls_t, tile, waves, res, 0, dw, gs)
             out = dev_empty(n, tdt, 1)
             if cls_t == 3:
                 out.copy_(x0)
@@ -273,6 +278,6 @@ def test_launch_shape_never_changes_bits(ctx, zg, cls_t, tdt):
             got = host(out).tobytes()
             if ref is None:
                 ref = got
-            assert got == ref, (tile, waves, res)
+            assert got == ref, (tile, waves, res, dw, gs)
     finally:
         ctx.zg_set_tune(cls_t, *saved)

@@ -11,36 +11,16 @@ import subprocess
 import numpy as np
 import pytest
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-CSRC = os.path.join(HERE, "..", "paper_2405_19493_amd", "csrc")
-INCLUDE = os.path.join(HERE, "..", "include")
-
-
-def _prepare(dst):
-    k = open(os.path.join(CSRC, "zg_kernels.hip")).read()
-    k = k.replace("extern __shared__", "extern").replace("__shared__", "static")
-    k = k.replace("#include <hip/hip_runtime.h>", '#include "hip/hip_runtime.h"')
-    open(os.path.join(dst, "zg_kernels_emu.cpp"), "w").write(k)
-    h = open(os.path.join(CSRC, "zg_internal.h")).read()
-    h = h.replace('"../../include/zg.h"', '"zg.h"')
-    assert "constexpr uint32_t SEQ_WINDOWS = 16;" in h
-    h = h.replace("constexpr uint32_t SEQ_WINDOWS = 16;", "constexpr uint32_t SEQ_WINDOWS = 1;")
-    open(os.path.join(dst, "zg_internal.h"), "w").write(h)
-    for name, src in (("zg_table.cpp", CSRC), ("zg.h", INCLUDE)):
-        open(os.path.join(dst, name), "w").write(open(os.path.join(src, name)).read())
+import kernel_emu
 
 
 @pytest.fixture(scope="module")
 def emu(tmp_path_factory):
     d = str(tmp_path_factory.mktemp("seq_emu"))
-    _prepare(d)
-    exe = os.path.join(d, "seq_emu")
-    r = subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address",
-                        "-fno-omit-frame-pointer", "-I", os.path.join(HERE, "host", "shim"),
-                        "-I", d, os.path.join(HERE, "host", "seq_emu.cpp"), "-o", exe,
-                        "-lpthread"], capture_output=True, text=True)
-    if r.returncode != 0:
-        pytest.fail(r.stdout[-3000:] + r.stderr[-3000:])
+    try:
+        exe = kernel_emu.build(d, seq_windows=1)
+    except RuntimeError as e:
+        pytest.fail(str(e))
     return d, exe
 
 
