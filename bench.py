@@ -38,8 +38,10 @@ def parse():
                         "printed as its own JSON line)")
     p.add_argument("--serve-seconds", type=float, default=5.0,
                    help="serving-loop run per mode (open-loop Poisson, 20k requests/s); 0 = skip")
-    p.add_argument("--no-autotune", action="store_true",
-                   help="skip the launch-shape autotuner (zg_autotune) and time the defaults")
+    p.add_argument("--autotune", action="store_true",
+                   help="run the launch-shape autotuner (zg_autotune) first; by default the "
+                        "library's default shapes are timed (chosen from a sweep of every "
+                        "candidate shape on these workloads)")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the LCG, batch and mutation rows (profiling runs)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -315,7 +317,7 @@ def main():
 
     n = N_STREAMS * N_PER
     ctx = Z.Context(0)
-    if not args.no_autotune:
+    if args.autotune:
         # the launch shape that is fastest on this device, at this size; cached
         # per device so that later runs (a profiler's) time the same shape
         import tempfile
@@ -383,7 +385,7 @@ def main():
                    "launch": {"kernel": "wave-specialised" if tune[4] else "block-pooled",
                               "tile": tune[0], "waves_per_block": tune[1],
                               "persistent_blocks_per_cu": tune[2], "drain_waves": tune[4],
-                              "group_steps": tune[5], "autotuned": not args.no_autotune},
+                              "group_steps": tune[5], "autotuned": bool(args.autotune)},
                    "variates_per_step": n, "streams": N_STREAMS, "per_stream": N_PER},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -186,7 +186,12 @@ static int fill_only(char **a) {
   const uint32_t hd = (uint32_t)std::min<uint64_t>(h, n);
   std::fprintf(stderr, "fill op=%u n=%llu head=%u drain=%u\n", op, (unsigned long long)n, hd,
                n_drain);
-  if (launch_fill(J, T, ZG_MAX_DRAWS, flags, 1024, 16, hd, 0, 2, n_drain, gsteps, nullptr) !=
+  // the block-pooled kernel's shape: EMU_TILE, EMU_WAVES, EMU_RES (persistent
+  // workgroups per compute unit) override 1024 x 16 x 2
+  const char *et = getenv("EMU_TILE"), *ew = getenv("EMU_WAVES"), *er = getenv("EMU_RES");
+  const uint32_t tile = et ? (uint32_t)atoi(et) : 1024, waves = ew ? (uint32_t)atoi(ew) : 16;
+  const uint32_t res = er ? (uint32_t)atoi(er) : 2;
+  if (launch_fill(J, T, ZG_MAX_DRAWS, flags, tile, waves, hd, 0, res, n_drain, gsteps, nullptr) !=
       hipSuccess)
     return 4;
   FILE *f = fopen(outfile, "wb");
