@@ -11,7 +11,7 @@ import subprocess
 
 import numpy as np
 
-from . import table_mp
+from . import table_mp, table_mz
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "zg_oracle.c")
@@ -109,8 +109,120 @@ def lib():
         L.orc_fill_streams_polar.restype = u64
         L.orc_seq_f64.argtypes = [vp, i32, u64, u32, u64, u64, vp, u64, vp, vp, vp, vp]
         L.orc_seq_f64.restype = u64
+        L.orc_lcg_long.argtypes = [u64, u32, u64, u32]
+        L.orc_lcg_long.restype = u64
+        L.orc_long_word.argtypes = [i32, u64, u32, u64, u32]
+        L.orc_long_word.restype = u64
+        L.orc_mz_f64.argtypes = [vp, i32, u64, u32, u64, u32, vp]
+        L.orc_mz_f64.restype = ctypes.c_double
+        L.orc_mz_f64_tape.argtypes = [vp, vp, u32, u32, vp, vp, u32, vp]
+        L.orc_mz_f64_tape.restype = ctypes.c_double
+        L.orc_mz_first.argtypes = [vp, u64, vp, vp]
+        L.orc_mz_first.restype = i32
+        L.orc_mz_region.argtypes = [vp, u64, u64]
+        L.orc_mz_region.restype = i32
+        L.orc_mz_attempt.argtypes = [vp, i32, u64, u64, vp]
+        L.orc_mz_attempt.restype = i32
+        L.orc_mz_enum.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.orc_mz_enum.restype = i32
+        L.orc_fill_streams_mz.argtypes = [vp, i32, u64, u32, u32, u64, u64, u32, vp, vp, i32]
+        L.orc_fill_streams_mz.restype = u64
         _lib = L
     return _lib
+
+
+class OrcMzTable(ctypes.Structure):
+    """The C struct of McFarland's modified ziggurat table (orc_mz_table)."""
+    _fields_ = [
+        ("n_buckets", ctypes.c_int), ("n_layers", ctypes.c_int), ("bits", ctypes.c_int),
+        ("ubits", ctypes.c_int),
+        ("xs", ctypes.c_double * 256), ("x0", ctypes.c_double),
+        ("ox", ctypes.c_double * 257), ("odx", ctypes.c_double * 257),
+        ("oy", ctypes.c_double * 257), ("ody", ctypes.c_double * 257),
+        ("kind", ctypes.c_int * 257), ("thr", ctypes.c_uint64 * 256),
+        ("alias", ctypes.c_int * 256),
+    ]
+
+
+_mz_table = None
+
+
+def mz_struct(t):
+    """The C struct of a modified-ziggurat table dict (oracle/table_mz.py)."""
+    T = OrcMzTable()
+    T.n_buckets, T.n_layers, T.bits, T.ubits = t["n_buckets"], t["n_layers"], t["bits"], t["ubits"]
+    for i, v in enumerate(t["xs"]):
+        T.xs[i] = v
+    T.x0 = t["x0"]
+    for k in range(t["n_layers"] + 1):
+        T.ox[k], T.odx[k], T.oy[k], T.ody[k] = t["ox"][k], t["odx"][k], t["oy"][k], t["ody"][k]
+        T.kind[k] = t["kind"][k]
+    for j in range(t["n_buckets"]):
+        T.thr[j] = int(t["thr"][j])
+        T.alias[j] = t["alias"][j]
+    return T
+
+
+def mz_table():
+    """The stored 256-bucket modified-ziggurat table as the C struct."""
+    global _mz_table
+    if _mz_table is None:
+        _mz_table = mz_struct(table_mz.load())
+    return _mz_table
+
+
+def long_word(kind, seed, s, v, d):
+    """nextLong word of draw d (the modified ziggurat's words)."""
+    return int(lib().orc_long_word(kind, seed & (2**64 - 1), s, v, d))
+
+
+def fill_mz(kind, seed, s, first, n, dmax=DMAX, nthreads=0, T=None):
+    """Modified-ziggurat variates first..first+n-1 of one stream; returns
+    (values, outcome codes, errors)."""
+    return fill_streams_mz(kind, seed, s, 1, first, n, dmax, nthreads, T)
+
+
+def fill_streams_mz(kind, seed, s0, n_streams, first, n_per, dmax=DMAX, nthreads=0, T=None):
+    n = n_streams * n_per
+    out = np.empty(n, dtype=np.float64)
+    cls = np.empty(n, dtype=np.uint8)
+    errs = lib().orc_fill_streams_mz(ctypes.byref(T or mz_table()), kind, seed & (2**64 - 1),
+                                     s0, n_streams, first, n_per, dmax, _p(out), _p(cls),
+                                     _threads(nthreads))
+    return out, cls, int(errs)
+
+
+def mz_tape(tape, dmax=DMAX, T=None, L=None):
+    """One modified-ziggurat variate from crafted words; (value, outcome code,
+    draw indices read)."""
+    L = L or lib()
+    arr = np.ascontiguousarray(tape, dtype=np.uint64)
+    reads = np.zeros(4 * dmax + 8, dtype=np.uint32)
+    nreads = ctypes.c_uint32()
+    cls = ctypes.c_uint8()
+    x = L.orc_mz_f64_tape(ctypes.byref(T or mz_table()), _p(arr), arr.size, dmax,
+                          ctypes.byref(cls), _p(reads), reads.size, ctypes.byref(nreads))
+    return x, cls.value, reads[:min(nreads.value, reads.size)].tolist()
+
+
+def mz_enum(T, edges, L=None):
+    """Exhaustive enumeration of a tiny modified-ziggurat format through the
+    oracle's own steps (orc_mz_enum): (layer weights per signed bin, region
+    counts per sign [r][neg], accepted weights per region and bin of the
+    magnitude, accepted totals per region)."""
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    nb = e.size - 1
+    nl = T.n_layers
+    lb = np.zeros(nb, dtype=np.uint64)
+    cnt = np.zeros(2 * (nl + 1), dtype=np.uint64)
+    acc = np.zeros((nl + 1) * nb, dtype=np.uint64)
+    tot = np.zeros(nl + 1, dtype=np.uint64)
+    rc = (L or lib()).orc_mz_enum(ctypes.byref(T), _p(e), nb, _p(lb), _p(cnt), _p(acc), _p(tot))
+    if rc == -1:
+        raise ValueError("format too large to enumerate")
+    if rc != 0:
+        raise ValueError("a region index outside the table")
+    return lb, cnt.reshape(nl + 1, 2), acc.reshape(nl + 1, nb), tot
 
 
 def table_dict():

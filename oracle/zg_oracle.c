@@ -187,10 +187,15 @@ typedef struct {
   uint32_t nreads, nreads_max;
 } orc_src;
 
+static uint64_t orc_long_word_(int kind, uint64_t seed, uint32_t s, uint64_t v, uint32_t d);
+
+/* kind > 0: the original ziggurat's words; kind < 0: nextLong words of the
+ * source -kind (the modified ziggurat); 0: the tape. */
 static uint64_t src_word(orc_src *S, uint32_t d) {
   if (S->reads && S->nreads < S->nreads_max) S->reads[S->nreads] = d;
   if (S->reads) S->nreads++;
   if (S->kind == 0) return d < S->ntape ? S->tape[d] : 0;
+  if (S->kind < 0) return orc_long_word_(-S->kind, S->seed, S->s, S->v, d);
   return orc_word(S->kind, S->seed, S->s, S->v, d);
 }
 
@@ -475,11 +480,242 @@ static int polar_pair(int kind, uint64_t seed, uint32_t s, uint64_t p, uint32_t 
   }
 }
 
+/* ---------------------------------------- McFarland's modified ziggurat */
+/*
+ * The comparator of Sections 1 and 3 (McFarland 2016; Java 17's Gaussian for
+ * SplittableRandom and the newer generators), as read here (the paper gives
+ * none of its steps; oracle/table_mz.py states the table):
+ *  - N equal-probability buckets (256), L layers (253) of mass T/N each, every
+ *    layer [0, X_i] x [Y_{i-1}, Y_i] wholly under f; the other N - L buckets'
+ *    mass lies in L + 1 regions (tail beyond X_0, an overhang right of each
+ *    layer, the cap above the top layer), picked by an alias table.
+ *  - First word W1 as a signed B-bit integer (B = 64).  Its low log2 N bits
+ *    are the bucket: a layer i < L returns x = X_i 2^-(B-1) * W1 at once (sign
+ *    and magnitude from W1 itself).  These are the low-order bits Section 3
+ *    says the method needs to be good.
+ *  - Otherwise the sign is W1's top bit, and the region is bucket j = the low
+ *    bits of the second word W2, or its alias when W1's other B-1 bits are at
+ *    or above the bucket's threshold.
+ *  - Region 0, the tail: pairs of words d, d+1 give E1 = -log U1+, E2 =
+ *    -log U2+ and a = E1 / X_0; accept X_0 + a iff a^2/2 < E2 (Marsaglia's
+ *    tail method); else the next pair.
+ *  - Overhang k: pairs of words give integers a, b (top ubits bits); in the
+ *    box [X_k, X_{k-1}] x [Y_{k-1}, Y_k], s = distance from the right edge,
+ *    t = height above the bottom, both in units of the box, so the curve runs
+ *    from (0, 0) to (1, 1) and the chord is t = s.  Convex strips (X_k >= 1:
+ *    the curve lies under the chord) take (s, t) = (max, min) of (a, b), a
+ *    uniform point under the chord; concave strips (X_{k-1} <= 1: the curve
+ *    lies over the chord) accept at once when t <= s; otherwise (and for the
+ *    strip holding x = 1) accept x = X_{k-1} - s dx iff
+ *    Y_{k-1} + t dy < exp(-x^2/2); else the next pair, same region.
+ *  - Words: the SplitMix64 word, or for java.util.Random its nextLong
+ *    ((next(32) << 32) + next(32), the LCG steps 2m+1 and 2m+2 of the keyed
+ *    double index m).  Draws 0 and 1 are W1 and W2, pairs from draw 2; the
+ *    draw budget and the NaN are the original ziggurat's.
+ */
+typedef struct {
+  int n_buckets;          /* N, a power of two <= 256 */
+  int n_layers;           /* L < N */
+  int bits;               /* B: bits of a word (64 in the real format) */
+  int ubits;              /* bits of a slow-path uniform (53 in the real format) */
+  double xs[256];         /* X_i 2^-(B-1), i < L */
+  double x0;              /* X_0 */
+  double ox[257], odx[257], oy[257], ody[257];   /* overhang k >= 1: X_{k-1}, X_{k-1} - X_k, Y_{k-1}, Y_k - Y_{k-1} */
+  int kind[257];          /* 0 tail, 1 convex, 2 concave, 3 the strip holding x = 1 */
+  uint64_t thr[256];      /* in units of 2^-(B-1) */
+  int alias[256];
+} orc_mz_table;
+
+/* nextLong of Random(seed) at the keyed double index of (s, v, d): the same
+ * two LCG steps as orc_lcg_word, combined as (int)(S1 >> 16) << 32 plus the
+ * sign-extended (int)(S2 >> 16). */
+uint64_t orc_lcg_long(uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  uint64_t m = (uint64_t)s * LCG_STREAM + (uint64_t)d * LCG_WINDOW + v;
+  uint64_t S1 = orc_lcg_state(seed, 2 * m + 1);
+  uint64_t S2 = orc_lcg_step(S1);
+  int32_t hi = (int32_t)(uint32_t)(S1 >> 16), lo = (int32_t)(uint32_t)(S2 >> 16);
+  return ((uint64_t)(int64_t)hi << 32) + (uint64_t)(int64_t)lo;
+}
+
+/* The word of draw d for the modified ziggurat: nextLong of each source. */
+uint64_t orc_long_word(int kind, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  return kind == ORC_LCG48 ? orc_lcg_long(seed, s, v, d) : orc_sm64_word(seed, s, v, d);
+}
+static uint64_t orc_long_word_(int kind, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  return orc_long_word(kind, seed, s, v, d);
+}
+
+static uint64_t mz_mask(int bits) { return bits >= 64 ? ~0ULL : ((1ULL << bits) - 1); }
+static int64_t mz_signed(const orc_mz_table *T, uint64_t W) {
+  return (int64_t)(W << (64 - T->bits)) >> (64 - T->bits);
+}
+
+/* Step 1: the first word.  Returns 1 and the signed x when its bucket is a
+ * layer; otherwise 0, the sign in *neg. */
+static int mz_first(const orc_mz_table *T, uint64_t W1, double *x, int *neg) {
+  int i = (int)(W1 & (uint64_t)(T->n_buckets - 1));
+  int64_t sv = mz_signed(T, W1);
+  *neg = sv < 0;
+  if (i < T->n_layers) {
+    *x = T->xs[i] * (double)sv;
+    return 1;
+  }
+  return 0;
+}
+
+/* Step 2: the region of a slow variate from W1's other bits and W2's bucket. */
+static int mz_region(const orc_mz_table *T, uint64_t W1, uint64_t W2) {
+  uint64_t u = W1 & mz_mask(T->bits - 1);
+  int j = (int)(W2 & (uint64_t)(T->n_buckets - 1));
+  return u < T->thr[j] ? j : T->alias[j];
+}
+
+/* Step 3: one attempt in region k with the pair of words (Wa, Wb); returns 1
+ * and the magnitude on acceptance. */
+static int mz_attempt(const orc_mz_table *T, int k, uint64_t Wa, uint64_t Wb, double *x) {
+  const int sh = T->bits - T->ubits;
+  const double g = ldexp(1.0, -T->ubits);
+  uint64_t a = (Wa & mz_mask(T->bits)) >> sh, b = (Wb & mz_mask(T->bits)) >> sh;
+  if (k == 0) {
+    double e1 = -log((double)(a + 1) * g), e2 = -log((double)(b + 1) * g);
+    double t = e1 / T->x0;
+    *x = T->x0 + t;
+    return 0.5 * (t * t) < e2;
+  }
+  uint64_t si = a, ti = b;
+  if (T->kind[k] == 1 && b > a) {
+    si = b;
+    ti = a;
+  }
+  *x = T->ox[k] - ((double)si * g) * T->odx[k];
+  if (T->kind[k] == 2 && ti <= si) return 1;
+  double y = T->oy[k] + ((double)ti * g) * T->ody[k];
+  return y < exp(-0.5 * (*x * *x));
+}
+
+/* One FP64 standard normal from a word source.  Outcome path: 0 layer,
+ * 1 overhang, 2 tail, 3 budget. */
+static double mz_f64_src(const orc_mz_table *T, orc_src *S, uint32_t dmax, uint8_t *cls) {
+  double x;
+  int neg;
+  if (dmax < 1) {
+    *cls = outcome(3, 1);
+    return nan64();
+  }
+  const uint64_t W1 = src_word(S, 0);
+  if (mz_first(T, W1, &x, &neg)) {
+    *cls = outcome(0, 1);
+    return x;
+  }
+  if (dmax < 2) {
+    *cls = outcome(3, 1);
+    return nan64();
+  }
+  int k = mz_region(T, W1, src_word(S, 1));
+  int attempts = 1;
+  for (uint32_t d = 2;; d += 2, ++attempts) {
+    if (d + 1 >= dmax) {
+      *cls = outcome(3, attempts);
+      return nan64();
+    }
+    const uint64_t Wa = src_word(S, d);
+    const uint64_t Wb = src_word(S, d + 1);
+    if (mz_attempt(T, k, Wa, Wb, &x)) {
+      *cls = outcome(k == 0 ? 2 : 1, attempts);
+      return neg ? -x : x;
+    }
+  }
+}
+
+double orc_mz_f64(const orc_mz_table *T, int kind, uint64_t seed, uint32_t s, uint64_t v,
+                  uint32_t dmax, uint8_t *cls) {
+  orc_src S = {-kind, seed, s, v, 0, 0, 0, 0, 0};
+  return mz_f64_src(T, &S, dmax, cls);
+}
+
+/* One variate from crafted words (word d = tape[d], 0 past the tape). */
+double orc_mz_f64_tape(const orc_mz_table *T, const uint64_t *tape, uint32_t ntape,
+                       uint32_t dmax, uint8_t *cls, uint32_t *reads, uint32_t nreads_max,
+                       uint32_t *nreads) {
+  orc_src S = {0, 0, 0, 0, tape, ntape, reads, 0, nreads_max};
+  double x = mz_f64_src(T, &S, dmax, cls);
+  if (nreads) *nreads = S.nreads;
+  return x;
+}
+
+/* The steps one at a time, for crafted words and enumeration. */
+int orc_mz_first(const orc_mz_table *T, uint64_t W1, double *x, int *neg) {
+  return mz_first(T, W1, x, neg);
+}
+int orc_mz_region(const orc_mz_table *T, uint64_t W1, uint64_t W2) {
+  return mz_region(T, W1, W2);
+}
+int orc_mz_attempt(const orc_mz_table *T, int k, uint64_t Wa, uint64_t Wb, double *x) {
+  return mz_attempt(T, k, Wa, Wb, x);
+}
+
+/* Exhaustive enumeration of a tiny format (B bits) through the three steps
+ * above.  The law of one variate: every first word (weight 1 of 2^B) either
+ * returns a layer's signed x (binned by signed value into layer_bins), or is
+ * slow with a sign; with each of the N buckets of the second word it picks a
+ * region: cnt[2 r + neg] counts those (first word, bucket) pairs.  Within a
+ * region, the accepted attempts over all 2^ubits x 2^ubits pairs of (a, b)
+ * give the conditional law of the magnitude (acc[r][bin] over the bins of
+ * the positive edges, acc_tot[r]).  Words carry a in their top ubits bits.
+ * edges: nb + 1 increasing bin edges (signed for layer_bins; the bins with
+ * edges >= 0 serve the magnitudes).  layer_bins[nb], cnt[2 (L+1)],
+ * acc[(L+1) nb], acc_tot[L+1].  Returns 0, -1 if the format is too large,
+ * -2 if a region index falls outside 0..L. */
+int orc_mz_enum(const orc_mz_table *T, const double *edges, int nb, uint64_t *layer_bins,
+                uint64_t *cnt, uint64_t *acc, uint64_t *acc_tot) {
+  if (T->bits > 24 || T->ubits > 12 || T->ubits > T->bits) return -1;
+  const uint64_t nw = 1ULL << T->bits;
+  const int N = T->n_buckets, L = T->n_layers;
+  memset(layer_bins, 0, sizeof(uint64_t) * nb);
+  memset(cnt, 0, sizeof(uint64_t) * 2 * (L + 1));
+  memset(acc, 0, sizeof(uint64_t) * (L + 1) * nb);
+  memset(acc_tot, 0, sizeof(uint64_t) * (L + 1));
+  for (uint64_t W1 = 0; W1 < nw; ++W1) {
+    double x;
+    int neg;
+    if (mz_first(T, W1, &x, &neg)) {
+      for (int b = 0; b < nb; ++b)
+        if (x >= edges[b] && x < edges[b + 1]) {
+          layer_bins[b]++;
+          break;
+        }
+      continue;
+    }
+    for (int j = 0; j < N; ++j) {
+      const int r = mz_region(T, W1, (uint64_t)j);
+      if (r < 0 || r > L) return -2;
+      cnt[2 * r + neg]++;
+    }
+  }
+  const uint64_t G = 1ULL << T->ubits;
+  const int sh = T->bits - T->ubits;
+  for (int r = 0; r <= L; ++r) {
+    if (!cnt[2 * r] && !cnt[2 * r + 1]) continue;
+    for (uint64_t a = 0; a < G; ++a)
+      for (uint64_t b = 0; b < G; ++b) {
+        double x;
+        if (!mz_attempt(T, r, a << sh, b << sh, &x)) continue;
+        acc_tot[r]++;
+        for (int k = 0; k < nb; ++k)
+          if (x >= edges[k] && x < edges[k + 1]) {
+            acc[(uint64_t)r * nb + k]++;
+            break;
+          }
+      }
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------ bulk fills */
 
 typedef struct {
   const orc_table *T;
-  int op; /* 0 zig f64, 1 zig f32, 2 polar f64, 3 mutate f64 */
+  int op; /* 0 zig f64, 1 zig f32, 2 polar f64, 3 mutate f64, 4 modified ziggurat f64 */
   int kind;
   uint64_t seed;
   uint32_t s;
@@ -492,6 +728,7 @@ typedef struct {
   uint8_t *cls;
   uint64_t errors;
   uint64_t n_per;   /* > 0: element k is variate first + k % n_per of stream s + k / n_per */
+  const orc_mz_table *M;   /* op 4 */
 } orc_job;
 
 static void *run_job(void *arg) {
@@ -513,6 +750,8 @@ static void *run_job(void *arg) {
       int ok = polar_pair(J->kind, J->seed, s, v >> 1, J->dmax, &o1, &o2, &att);
       ((double *)J->out)[k] = (v & 1) ? o2 : o1;
       c = (uint8_t)(ok ? ((att - 1 > 63 ? 63 : att - 1) << 2) : (3 | ((att - 1 > 63 ? 63 : att - 1) << 2)));
+    } else if (J->op == 4) {
+      ((double *)J->out)[k] = orc_mz_f64(J->M, J->kind, J->seed, s, v, J->dmax, &c);
     } else {
       double z = orc_zig_f64(J->T, J->kind, J->seed, s, v, J->dmax, &c);
       double *x = (double *)J->out;
@@ -579,6 +818,15 @@ uint64_t orc_fill_streams_polar(int kind, uint64_t seed, uint32_t s0, uint32_t n
                                 uint64_t first, uint64_t n_per, uint32_t dmax, double *out,
                                 uint8_t *cls, int nthreads) {
   orc_job j = {0, 2, kind, seed, s0, first, 0, 0, dmax, 0.0, out, 0, cls, 0, n_per};
+  return run_split(j, (uint64_t)n_streams * n_per, nthreads);
+}
+
+/* The modified ziggurat: variates first .. first + n_per - 1 of streams
+ * s0 .. s0 + n_streams - 1, stream-major (n_streams = 1: one stream). */
+uint64_t orc_fill_streams_mz(const orc_mz_table *M, int kind, uint64_t seed, uint32_t s0,
+                             uint32_t n_streams, uint64_t first, uint64_t n_per, uint32_t dmax,
+                             double *out, uint8_t *cls, int nthreads) {
+  orc_job j = {0, 4, kind, seed, s0, first, 0, 0, dmax, 0.0, out, 0, cls, 0, n_per, M};
   return run_split(j, (uint64_t)n_streams * n_per, nthreads);
 }
 
