@@ -61,7 +61,7 @@ typedef int32_t zg_status;
 #define ZG_ESTATE (-7)   /* object in the wrong state (server stopped, ...) */
 
 typedef enum { ZG_SPLITMIX64 = 1, ZG_JAVA_LCG48 = 2 } zg_kind;
-typedef enum { ZG_ZIGGURAT = 0, ZG_POLAR = 1 } zg_method;
+typedef enum { ZG_ZIGGURAT = 0, ZG_POLAR = 1, ZG_MCFARLAND = 2 } zg_method;
 typedef enum { ZG_F64 = 0, ZG_F32 = 1 } zg_dtype;
 
 #define ZG_LAYERS 128
@@ -104,6 +104,46 @@ typedef struct zg_table_view {
 /* Builds the table on the host (no device needed).  out: caller-owned. */
 zg_status zg_build_table(zg_table_view *out);
 
+/* The modified ziggurat's table (McFarland's method: the comparator that
+ * Sections 1 and 3 measure, whose need for good low-order bits Section 3
+ * discusses; the paper gives none of its steps, so this is the published
+ * method as read here).  f(x) = exp(-x^2/2) on x >= 0, total mass
+ * sqrt(pi/2); 256 buckets of mass A = sqrt(pi/2)/256.  Layers lie wholly
+ * under f, built from the bottom: X_0 f(X_0) = A with X_0 > 1, then
+ * X_i (f(X_i) - Y_{i-1}) = A with Y_i = f(X_i), as many as fit
+ * (ZG_MZ_LAYERS).  The rest of the mass lies in ZG_MZ_LAYERS + 1 regions:
+ * region 0 is the tail beyond X_0; region k >= 1 is the overhang
+ * {Y_{k-1} < y < f(x), X_k < x < X_{k-1}} (X_L = 0 and Y_L = 1: the cap).
+ *  xs[i] = X_i 2^-63 (i < ZG_MZ_LAYERS, 0 beyond); x0 = X_0;
+ *  ox[k] = X_{k-1}, odx[k] = X_{k-1} - X_k, oy[k] = Y_{k-1},
+ *  ody[k] = Y_k - Y_{k-1} (k >= 1; entry 0 unused);
+ *  kind[k]: 0 tail, 1 convex (X_k >= 1), 2 concave (X_{k-1} <= 1), 3 the
+ *  strip holding x = 1;
+ *  thr[j], alias[j]: bucket j gives region j while the 63 low bits of the
+ *  first word are below thr[j] (units of 2^-63), else region alias[j].
+ * Region masses a_k are rounded to integers m_k = round(a_k / sum a 2^71),
+ * the excess taken from the largest (lowest index among equals); the alias
+ * table pairs the lowest-index bucket below 2^63 with the lowest-index one
+ * above, until none is left.  Every floating entry is the correctly rounded
+ * value of the exact quantity (double-double here). */
+#define ZG_MZ_BUCKETS 256
+#define ZG_MZ_LAYERS 253
+typedef struct zg_mz_table_view {
+  double x0;
+  double xs[ZG_MZ_BUCKETS];
+  double ox[ZG_MZ_LAYERS + 1], odx[ZG_MZ_LAYERS + 1], oy[ZG_MZ_LAYERS + 1],
+      ody[ZG_MZ_LAYERS + 1];
+  uint64_t thr[ZG_MZ_BUCKETS];
+  uint8_t kind[ZG_MZ_LAYERS + 1];
+  uint8_t alias[ZG_MZ_BUCKETS];
+} zg_mz_table_view;
+
+/* Builds the modified ziggurat's table on the host (no device needed).
+ * out: caller-owned.  ZG_EINVAL if the construction does not give
+ * ZG_MZ_LAYERS layers or fails its own checks (masses adding up to
+ * sqrt(pi/2), the alias table reproducing the masses). */
+zg_status zg_build_mz_table(zg_mz_table_view *out);
+
 /* ---------------------------------------------------------------- context */
 
 /* Creates a context on HIP device hip_device: builds the table, uploads it
@@ -138,9 +178,24 @@ zg_status zg_table(const zg_ctx *ctx, zg_table_view *out);
  *    pair p = v >> 1, attempt a uses W(p, 2a) and W(p, 2a+1):
  *    v1 = 2U-1, v2 = 2U-1, s = v1 v1 + v2 v2, reject s >= 1 or s == 0,
  *    m = sqrt(-2 log(s) / s); variate 2p is v1 m, variate 2p+1 is v2 m.
+ *  ZG_MCFARLAND (ZG_F64 only): the modified ziggurat (zg_mz_table_view).
+ *    Words are 64-bit longs L(d): the SplitMix64 word, or for ZG_JAVA_LCG48
+ *    nextLong = (next(32) << 32) + next(32) of LCG steps 2m+1, 2m+2 of the
+ *    keyed index m of (s, v, d).  L(0) read as a signed integer picks bucket
+ *    i = its low 8 bits; i < ZG_MZ_LAYERS gives x = xs[i] * (double)L(0).
+ *    Otherwise the sign is L(0)'s top bit and the region is j = the low 8
+ *    bits of L(1), or alias[j] when the 63 low bits of L(0) are >= thr[j].
+ *    Attempts take pairs (L(d), L(d+1)), d = 2, 4, ..., as 53-bit integers
+ *    a, b (top bits) and g = 2^-53.  Tail: t = -log((a+1) g) / x0,
+ *    x = x0 + t, accept iff 0.5 t t < -log((b+1) g).  Overhang k: (s, t) =
+ *    (a, b), or (max, min) of them where kind[k] == 1; x = ox[k] - (s g)
+ *    odx[k]; accept at once where kind[k] == 2 and t <= s; otherwise accept
+ *    iff oy[k] + (t g) ody[k] < exp(-0.5 x x).  A rejection takes the next
+ *    pair in the same region; a pair needing d + 1 >= 256 gives the NaN.
  * A variate that would need a word with d >= 256 becomes a quiet NaN and
  * raises ZG_FLAG_BUDGET (probability below 1e-200).
- * Errors: ZG_EINVAL (null, enum, alignment, stream limit, polar+F32),
+ * Errors: ZG_EINVAL (null, enum, alignment, stream limit, polar or
+ * McFarland with F32),
  * ZG_ERANGE (first_index + n past the window), ZG_EHIP. */
 zg_status zg_fill(zg_ctx *ctx, void *d_out, uint64_t n, zg_dtype dtype, zg_method method,
                   zg_kind kind, uint64_t seed, uint32_t stream, uint64_t first_index,

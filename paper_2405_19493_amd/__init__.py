@@ -30,6 +30,9 @@ ZG_SPLITMIX64 = 1
 ZG_JAVA_LCG48 = 2
 ZG_ZIGGURAT = 0
 ZG_POLAR = 1
+ZG_MCFARLAND = 2
+ZG_MZ_BUCKETS = 256
+ZG_MZ_LAYERS = 253
 ZG_F64 = 0
 ZG_F32 = 1
 ZG_FLAG_BUDGET = 1
@@ -70,6 +73,20 @@ class TableView(ctypes.Structure):
         ("w24", ctypes.c_float * 128),
         ("k53", ctypes.c_uint64 * 128),
         ("k24", ctypes.c_uint32 * 128),
+    ]
+
+
+class MzTableView(ctypes.Structure):
+    _fields_ = [
+        ("x0", ctypes.c_double),
+        ("xs", ctypes.c_double * 256),
+        ("ox", ctypes.c_double * 254),
+        ("odx", ctypes.c_double * 254),
+        ("oy", ctypes.c_double * 254),
+        ("ody", ctypes.c_double * 254),
+        ("thr", ctypes.c_uint64 * 256),
+        ("kind", ctypes.c_uint8 * 254),
+        ("alias", ctypes.c_uint8 * 256),
     ]
 
 
@@ -132,6 +149,7 @@ def _load():
     P, U64, U32, I32, D = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double
     sigs = {
         "zg_build_table": [P],
+        "zg_build_mz_table": [P],
         "zg_create": [ctypes.c_int, P],
         "zg_destroy": [P],
         "zg_table": [P, P],
@@ -222,6 +240,13 @@ def zg_build_table():
     """Host-only table build (no device needed)."""
     t = TableView()
     _check(lib.zg_build_table(ctypes.byref(t)), "zg_build_table")
+    return t
+
+
+def zg_build_mz_table():
+    """Host-only build of the modified ziggurat's table (no device needed)."""
+    t = MzTableView()
+    _check(lib.zg_build_mz_table(ctypes.byref(t)), "zg_build_mz_table")
     return t
 
 

@@ -30,7 +30,8 @@ uint32_t chunk_of(uint32_t op) { return op == OP_ZIG32 ? 256u : 128u; }
 
 int tune_class(uint32_t op) {
   switch (op) {
-    case OP_ZIG64: return ZG_TUNE_FILL_F64;
+    case OP_ZIG64:
+    case OP_MZ64: return ZG_TUNE_FILL_F64;
     case OP_ZIG32: return ZG_TUNE_FILL_F32;
     case OP_POLAR: return ZG_TUNE_POLAR;
     default: return ZG_TUNE_MUTATE;
@@ -60,15 +61,17 @@ zg_status check_gen(const void *out, uint64_t n_total, zg_dtype dtype, zg_method
                     uint64_t n_per, uint32_t *op) {
   if (kind != ZG_SPLITMIX64 && kind != ZG_JAVA_LCG48) return ZG_EINVAL;
   if (dtype != ZG_F64 && dtype != ZG_F32) return ZG_EINVAL;
-  if (method != ZG_ZIGGURAT && method != ZG_POLAR) return ZG_EINVAL;
-  if (method == ZG_POLAR && dtype != ZG_F64) return ZG_EINVAL;
+  if (method != ZG_ZIGGURAT && method != ZG_POLAR && method != ZG_MCFARLAND) return ZG_EINVAL;
+  if (method != ZG_ZIGGURAT && dtype != ZG_F64) return ZG_EINVAL;
   if (n_total > 0 && !out) return ZG_EINVAL;
   if (n_total >= (1ull << 40)) return ZG_EINVAL;   // queue entries hold 40-bit element indices
   size_t esz = dtype == ZG_F64 ? 8 : 4;
   if (((uintptr_t)out) % esz) return ZG_EINVAL;
   if (n_streams == 0 || (uint64_t)stream0 + n_streams > max_streams_of(kind)) return ZG_EINVAL;
   if (first + n_per < first || first + n_per > window_of(kind)) return ZG_ERANGE;
-  *op = method == ZG_POLAR ? OP_POLAR : (dtype == ZG_F32 ? OP_ZIG32 : OP_ZIG64);
+  *op = method == ZG_POLAR ? OP_POLAR
+        : method == ZG_MCFARLAND ? OP_MZ64
+        : (dtype == ZG_F32 ? OP_ZIG32 : OP_ZIG64);
   return ZG_OK;
 }
 
@@ -145,18 +148,12 @@ zg_status zg_create(int hip_device, zg_ctx **out) {
     delete ctx;
     return ZG_ENOMEM;
   }
-  std::memset(h, 0, sizeof(*h));
-  for (int i = 0; i < ZG_LAYERS; ++i) {
-    h->fast64[i] = {ctx->table.k53[i], ctx->table.w53[i]};
-    h->fast32[i] = {ctx->table.k24[i], ctx->table.w24[i]};
-    h->y[i] = ctx->table.y[i];
-    h->dy[i] = ctx->table.dy[i];
-    h->w53[i] = ctx->table.w53[i];
-    h->w24d[i] = ctx->table.w24d[i];
+  st = build_dev_tables(ctx->table, h);
+  if (st != ZG_OK) {
+    delete h;
+    delete ctx;
+    return st;
   }
-  h->r = ctx->table.r;
-  build_lcg_tables(&h->lcg);
-  build_log_tables(&h->logt);
   hipError_t e = hipMalloc(&ctx->d_tables, sizeof(DevTables));
   if (e == hipSuccess) e = hipMemcpy(ctx->d_tables, h, sizeof(DevTables), hipMemcpyHostToDevice);
   delete h;

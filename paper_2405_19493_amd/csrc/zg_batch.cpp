@@ -44,6 +44,7 @@ zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
     zg_dtype dt = r.op == ZG_OP_MUTATE ? ZG_F64 : (zg_dtype)r.dtype;
     zg_method me = r.op == ZG_OP_MUTATE ? ZG_ZIGGURAT : (zg_method)r.method;
     if (r.op == ZG_OP_MUTATE && (r.dtype != ZG_F64 || r.method != ZG_ZIGGURAT)) return ZG_EINVAL;
+    if (me == ZG_MCFARLAND) return ZG_EINVAL;   // plain fills only
     if (r.handle >= 0) {
       if ((uint32_t)r.handle >= ZG_MAX_HANDLES || !ctx->handles[r.handle].open) return ZG_ENOENT;
       const HandleInfo &h = ctx->handles[r.handle];

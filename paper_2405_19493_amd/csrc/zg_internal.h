@@ -35,6 +35,24 @@ struct Fast32 {
   float w;      // w24
 };
 
+// The modified ziggurat's slow-path tables (zg_mz_table_view): one region's
+// box, and one bucket's threshold and alias, each read as one unit.
+struct MzRegion {
+  double ox, odx, oy, ody;
+};
+struct MzBucket {
+  uint64_t thr;
+  uint32_t alias;
+  uint32_t pad;
+};
+struct MzTabs {
+  double xs[ZG_MZ_BUCKETS];
+  MzRegion region[ZG_MZ_LAYERS + 1];
+  MzBucket bucket[ZG_MZ_BUCKETS];
+  uint32_t kind[ZG_MZ_LAYERS + 3];
+  double x0;
+};
+
 // Everything the kernels read, in one device allocation per context.
 // Logarithm table of the polar method: for m in [sqrt(1/2), sqrt(2)) split
 // at the top 7 mantissa bits of its binade (index LOG_I0 + k), invc[k] is a
@@ -62,10 +80,11 @@ struct DevTables {
   double pad[7];
   LcgTables lcg;
   LogTables logt;
+  MzTabs mz;
 };
 
 // Operation selector shared by the plain and batch kernels.
-enum Op : uint32_t { OP_ZIG64 = 0, OP_ZIG32 = 1, OP_POLAR = 2, OP_MUTATE = 3 };
+enum Op : uint32_t { OP_ZIG64 = 0, OP_ZIG32 = 1, OP_POLAR = 2, OP_MUTATE = 3, OP_MZ64 = 4 };
 
 // One generation job over elements [0, n_streams * n_per) of an output:
 // element e is variate first + (e mod n_per) of stream s0 + e / n_per.
@@ -215,6 +234,11 @@ const void *kernel_batch_class(int cls);
 size_t batch_class_lds_bytes(int cls, uint32_t waves);
 
 zg_status build_table(zg_table_view *t);
+zg_status build_mz_table(zg_mz_table_view *t);
+// Everything the kernels read, from the layer table tv: the fast-path and
+// slow-path entries, the modified ziggurat's tables, the LCG jump tables and
+// the polar log table.
+zg_status build_dev_tables(const zg_table_view &tv, DevTables *h);
 void build_lcg_tables(LcgTables *L);
 void build_log_tables(LogTables *L);
 Affine lcg_power(uint64_t k);

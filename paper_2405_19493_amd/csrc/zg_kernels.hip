@@ -74,6 +74,14 @@ DEV uint64_t lcg_word_from(uint64_t S1) {
   return (((S1 >> 22) << 27) + (S2 >> 21)) << 11;
 }
 
+// java.util.Random's nextLong whose first LCG state (step 2m+1) is S1:
+// (next(32) << 32) + next(32), the second int sign-extended.
+DEV uint64_t lcg_long_from(uint64_t S1) {
+  const uint64_t S2 = (LCG_A * S1 + LCG_C) & LCG_M48;
+  const int64_t hi = (int32_t)(uint32_t)(S1 >> 16), lo = (int32_t)(uint32_t)(S2 >> 16);
+  return ((uint64_t)hi << 32) + (uint64_t)lo;
+}
+
 // The 53-bit integer j = bits 3..55 of a word (whi:wlo), as its two halves
 // (bit-field extracts, so that the conversion below stays two 32-bit ones).
 DEV uint32_t j_hi(uint32_t whi) { return __builtin_amdgcn_ubfe(whi, 3, 21); }
@@ -101,6 +109,15 @@ template <int KIND>
 DEV uint64_t wordk(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
   if (KIND == ZG_JAVA_LCG48)
     return lcg_word_from(lcg_jump(&T->lcg, lcg_state0(seed), 2 * lcg_index(s, v, d) + 1));
+  return sm64_word(seed, s, v, d);
+}
+
+// The modified ziggurat's long of draw d: the SplitMix64 word itself, or
+// nextLong of the LCG at the keyed index of (s, v, d).
+template <int KIND>
+DEV uint64_t longk(const DevTables *T, uint64_t seed, uint32_t s, uint64_t v, uint32_t d) {
+  if (KIND == ZG_JAVA_LCG48)
+    return lcg_long_from(lcg_jump(&T->lcg, lcg_state0(seed), 2 * lcg_index(s, v, d) + 1));
   return sm64_word(seed, s, v, d);
 }
 
@@ -371,6 +388,16 @@ DEV double fast64(const Fast64 *tab, uint64_t W, bool &fast) {
   return to_f64(jh, jl) * f.w;
 }
 
+// Modified ziggurat, fast path of one element: bucket i = the low byte of
+// the long; a layer (i < ZG_MZ_LAYERS) gives x = X_i 2^-63 times the long as
+// a signed integer (tab[i].w holds X_i 2^-63, 0 past the layers, so a slow
+// element's placeholder is 0).
+DEV double fast_mz(const Fast64 *tab, uint64_t W, bool &fast) {
+  const uint32_t i = (uint32_t)W & 255u;
+  fast = i < ZG_MZ_LAYERS;
+  return tab[i].w * (double)(int64_t)W;
+}
+
 // One polar step: a pair per lane (2 elements).
 template <int KIND>
 DEV void polar_step(const Job &J, const PolarCtx &C, const LaneConst &LC, Queue &Q, uint64_t ec,
@@ -509,6 +536,12 @@ struct BlockLds {
 // Loads the tables an op needs (whole block; no barrier).
 template <int OP>
 DEV void load_tabs(const DevTables *T, LdsTabs &L) {
+  if (OP == OP_MZ64) {
+    // modified ziggurat: the bucket multipliers in the FP64 fast-path slots
+    for (uint32_t i = threadIdx.x; i < ZG_MZ_BUCKETS; i += blockDim.x)
+      L.f64[i] = {0, T->mz.xs[i]};
+    return;
+  }
   for (uint32_t i = threadIdx.x; i < ZG_LAYERS; i += blockDim.x) {
     if (OP == OP_ZIG32) {
       const Fast32 f = T->fast32[i];
@@ -524,6 +557,85 @@ DEV void load_tabs(const DevTables *T, LdsTabs &L) {
   }
 }
 
+// ------------------------------------------- modified ziggurat, slow path
+
+// One attempt in region k with the longs (Wa, Wb): their top 53 bits a, b.
+// Tail (k = 0): t = -log((a+1) 2^-53) / x0, x = x0 + t, accepted iff
+// t^2/2 < -log((b+1) 2^-53).  Overhang k: (s, t) = (a, b), or (max, min)
+// in a convex strip; x = X_{k-1} - s dx; accepted at once in a concave strip
+// when t <= s, otherwise iff Y_{k-1} + t dy < exp(-x^2/2).
+DEV bool mz_attempt(const MzTabs &M, uint32_t k, uint64_t Wa, uint64_t Wb, double &x) {
+  constexpr double g = 0x1p-53;
+  const uint64_t a = Wa >> 11, b = Wb >> 11;
+  if (k == 0) {
+    const double e1 = -log((double)(a + 1) * g), e2 = -log((double)(b + 1) * g);
+    const double t = e1 / M.x0;
+    x = M.x0 + t;
+    return 0.5 * (t * t) < e2;
+  }
+  const uint32_t kind = M.kind[k];
+  uint64_t si = a, ti = b;
+  if (kind == 1 && b > a) {
+    si = b;
+    ti = a;
+  }
+  const MzRegion R = M.region[k];
+  x = R.ox - ((double)si * g) * R.odx;
+  if (kind == 2 && ti <= si) return true;
+  const double y = R.oy + ((double)ti * g) * R.ody;
+  return y < exp(-0.5 * (x * x));
+}
+
+// The modified ziggurat's variate v of stream s from draw d0 (0: from its
+// first long; else the draw of the next attempt pair), at most max_att
+// attempts.  Returns whether it is decided (value z: the signed variate, or
+// the NaN when the draw budget runs out); otherwise dn is the draw to resume
+// from.  The first long gives the bucket, sign and alias word; the second the
+// region's bucket.
+template <int KIND>
+DEV bool mz_run(const Job &J, const DevTables *T, uint32_t dmax, uint32_t s, uint64_t v,
+                uint32_t d0, uint32_t max_att, double &z, uint32_t &dn, bool &budget) {
+  const MzTabs &M = T->mz;
+  if (dmax < 1) {
+    budget = true;
+    z = nan64();
+    return true;
+  }
+  const uint64_t W1 = longk<KIND>(T, J.seed, s, v, 0);
+  const uint32_t i = (uint32_t)W1 & 255u;
+  if (i < ZG_MZ_LAYERS) {
+    z = M.xs[i] * (double)(int64_t)W1;
+    return true;
+  }
+  if (dmax < 2) {
+    budget = true;
+    z = nan64();
+    return true;
+  }
+  const uint64_t W2 = longk<KIND>(T, J.seed, s, v, 1);
+  const uint32_t j = (uint32_t)W2 & 255u;
+  const MzBucket B = M.bucket[j];
+  const uint32_t k = (W1 & 0x7FFFFFFFFFFFFFFFull) < B.thr ? j : B.alias;
+  const bool neg = (W1 >> 63) != 0;
+  uint32_t d = d0 < 2 ? 2 : d0;
+  for (uint32_t att = 0; att < max_att; ++att, d += 2) {
+    if (d + 1 >= dmax) {
+      budget = true;
+      z = nan64();
+      return true;
+    }
+    const uint64_t Wa = longk<KIND>(T, J.seed, s, v, d);
+    const uint64_t Wb = longk<KIND>(T, J.seed, s, v, d + 1);
+    double x;
+    if (mz_attempt(M, k, Wa, Wb, x)) {
+      z = neg ? -x : x;
+      return true;
+    }
+  }
+  dn = d;
+  return false;
+}
+
 // The whole attempt sequence of one variate from draw 0 (the same steps, in
 // the same order and precision, as attempt64 / attempt32): returns the signed
 // FP64 value, or for FP32 mode the FP32 value widened exactly to double, or
@@ -532,6 +644,11 @@ template <int OP, int KIND>
 DEV double resolve(const Job &J, const LdsTabs &L, const DevTables *T, double r, uint32_t dmax,
                    uint32_t s, uint64_t v, bool &budget, uint32_t d = 0) {
   double z;
+  if (OP == OP_MZ64) {
+    uint32_t dn;
+    mz_run<KIND>(J, T, dmax, s, v, d, 0xFFFFFFFFu, z, dn, budget);
+    return z;
+  }
   for (;;) {
     if (d >= dmax) {
       budget = true;
@@ -620,15 +737,20 @@ DEV uint32_t step_regs(const Job &J, const Fast64 *f64t, const Fast32 *f32t, con
   const uint32_t lane = lane_id();
   const uint64_t seed = J.seed;
   uint32_t b4 = 0;
-  if (OP == OP_ZIG64 || OP == OP_MUTATE) {
+  if (OP == OP_ZIG64 || OP == OP_MUTATE || OP == OP_MZ64) {
     constexpr uint32_t CH = 128;
     uint64_t W[4];
     if (LCG) {
-      W[0] = lcg_word_from(aff(LC.a[0], Sc));
-      W[1] = lcg_word_from(aff(LC.a[1], Sc));
+      // the two LCG states of a variate make its nextDouble word, or for the
+      // modified ziggurat its nextLong
+      const auto lw = [](uint64_t S1) {
+        return OP == OP_MZ64 ? lcg_long_from(S1) : lcg_word_from(S1);
+      };
+      W[0] = lw(aff(LC.a[0], Sc));
+      W[1] = lw(aff(LC.a[1], Sc));
       Sc = aff(T->lcg.jump[1][1], Sc);   // 256 steps = the next 128-element chunk
-      W[2] = lcg_word_from(aff(LC.a[0], Sc));
-      W[3] = lcg_word_from(aff(LC.a[1], Sc));
+      W[2] = lw(aff(LC.a[0], Sc));
+      W[3] = lw(aff(LC.a[1], Sc));
     } else {
       const uint64_t zc = seed + GAMMA * (1ull + ((uint64_t)s << 48) + vc);
       W[0] = mix64(zc + LC.g[0]);
@@ -641,8 +763,9 @@ DEV uint32_t step_regs(const Job &J, const Fast64 *f64t, const Fast32 *f32t, con
       const uint64_t ea = ec + u * CH + 2ull * lane;
       const bool ok0 = FULL || ea < e_end, ok1 = FULL || ea + 1 < e_end;
       bool fast0, fast1;
-      double x0 = fast64(f64t, W[2 * u], fast0);
-      double x1 = fast64(f64t, W[2 * u + 1], fast1);
+      double x0 = OP == OP_MZ64 ? fast_mz(f64t, W[2 * u], fast0) : fast64(f64t, W[2 * u], fast0);
+      double x1 = OP == OP_MZ64 ? fast_mz(f64t, W[2 * u + 1], fast1)
+                                : fast64(f64t, W[2 * u + 1], fast1);
       if (OP == OP_MUTATE) {
         const double *out = (const double *)J.out + ea;
         if (FULL || (ok0 && ok1)) {
@@ -742,6 +865,8 @@ DEV uint32_t step_general(const Job &J, const Fast64 *f64t, const Fast32 *f32t,
         const uint32_t j = u & 0xFFFFFFu;
         xf[t] = (float)j * f.w;
         fast = j < f.k;
+      } else if (OP == OP_MZ64) {
+        x[t] = fast_mz(f64t, longk<KIND>(T, J.seed, s, v, 0), fast);
       } else {
         x[t] = fast64(f64t, wordk<KIND>(T, J.seed, s, v, 0), fast);
         if (OP == OP_MUTATE) {
@@ -825,6 +950,8 @@ DEV bool attempt_at(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t
 template <int OP, int KIND>
 DEV bool first_step(const Job &J, const LdsTabs &L, const DevTables *T, uint32_t dmax, uint32_t s,
                     uint64_t v, double &z, uint32_t &d, bool &budget) {
+  // modified ziggurat: the region and its first attempt pair
+  if (OP == OP_MZ64) return mz_run<KIND>(J, T, dmax, s, v, 0, 1, z, d, budget);
   uint32_t i, neg;
   double x;
   d = 0;
@@ -1948,6 +2075,9 @@ hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t
     case OP_POLAR:
       return launch_kind<OP_POLAR>(J, T, dmax, flags, tile, waves, head, qcap, resident, n_drain,
                                    gsteps, stream);
+    case OP_MZ64:
+      return launch_kind<OP_MZ64>(J, T, dmax, flags, tile, waves, head, qcap, resident, n_drain,
+                                  gsteps, stream);
     default:
       return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, qcap, resident, n_drain,
                                     gsteps, stream);

@@ -1,5 +1,8 @@
-// Host-side construction of the 128-layer ziggurat table in double-double
-// arithmetic, and of the java.util.Random jump-ahead tables.
+// Host-side construction, in double-double arithmetic, of the 128-layer
+// ziggurat table and of the modified ziggurat's 256-bucket table (layers
+// found by bisection, region masses from the Maclaurin series of the
+// integral of f, alias table in exact integers), and of the java.util.Random
+// jump-ahead tables.
 //
 // Table (Section 1 / Section 2 "Ziggurat": the GSL-style original ziggurat of
 // Marsaglia-Tsang and Leong, 128 equal-area layers): f(x) = exp(-x^2/2);
@@ -14,6 +17,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
+#include <set>
+#include <vector>
 
 #include "zg_internal.h"
 
@@ -153,7 +159,163 @@ uint64_t floor_u64(dd x) {
   return (uint64_t)fl;
 }
 
+// ------------------------------------------------ modified ziggurat table
+
+// pi to about 107 bits.
+const dd PI = {0x1.921fb54442d18p+1, 0x1.1a62633145c07p-53};
+
+// F(x): the integral of f over [0, x], by its Maclaurin series
+// sum_n (-x^2/2)^n x / (n! (2n + 1)).  Below x = 4 the largest term is about
+// 2^9 times the sum, and the terms fall under 1e-40 before n = 90.
+dd F_of(dd x) {
+  const dd q = neg(mul_pow2(mul(x, x), 0.5));
+  dd p = x;   // q^n x / n!
+  dd sum = x;
+  for (int n = 1; n < 160; ++n) {
+    p = divide(mul(p, q), mk((double)n));
+    const dd t = divide(p, mk((double)(2 * n + 1)));
+    sum = add(sum, t);
+    if (n > 16 && std::fabs(t.hi) < 1e-40) break;
+  }
+  return sum;
+}
+
+// x (f(x) - ylo) - A: the mass of the box [0, x] x [ylo, f(x)] less a bucket's.
+dd box_excess(dd x, dd ylo, dd A) { return sub(mul(x, sub(f_of(x), ylo)), A); }
+
+// The root of box_excess in [lo, hi], where it falls from above 0 to below.
+dd box_root(dd lo, dd hi, dd ylo, dd A) {
+  for (int it = 0; it < 120; ++it) {
+    const dd mid = mul_pow2(add(lo, hi), 0.5);
+    if (box_excess(mid, ylo, A).hi > 0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return mul_pow2(add(lo, hi), 0.5);
+}
+
+// Nearest integer of a non-negative dd value below 2^100.
+unsigned __int128 nint_u128(dd x) {
+  const dd n = fast_two_sum(x.hi, x.lo);
+  const double fh = std::floor(n.hi);
+  const double frac = (n.hi - fh) + n.lo;
+  return (unsigned __int128)fh + (unsigned __int128)(__int128)std::floor(frac + 0.5);
+}
+
 }  // namespace
+
+zg_status build_mz_table(zg_mz_table_view *t) {
+  constexpr int N = ZG_MZ_BUCKETS;
+  std::memset(t, 0, sizeof(*t));
+  const dd T = dd_sqrt(mul_pow2(PI, 0.5));   // mass of f on x >= 0
+  const dd A = mul_pow2(T, 1.0 / N);
+  const dd one = mk(1.0);
+  // layers from the bottom: layer 0 solves x f(x) = A right of x = 1
+  dd X[N], Y[N];
+  X[0] = box_root(one, mk(8.0), mk(0.0), A);
+  Y[0] = f_of(X[0]);
+  int L = 1;
+  while (L < N) {
+    const dd ylo = Y[L - 1];
+    // the box over ylo is heaviest where f(x) (1 - x^2) = ylo, left of x = 1
+    // (that slope falls on (0, 1)); no layer fits unless it beats A there
+    const auto slope = [&](double x) { return std::exp(-0.5 * x * x) * (1.0 - x * x) - ylo.hi; };
+    double a = 0.0, b = std::min(1.0, X[L - 1].hi);
+    if (slope(b) >= 0) {
+      a = b;
+    } else {
+      for (int it = 0; it < 200; ++it) {
+        const double m = 0.5 * (a + b);
+        if (slope(m) > 0)
+          a = m;
+        else
+          b = m;
+      }
+    }
+    if (!(box_excess(mk(a), ylo, A).hi > 0)) break;
+    X[L] = box_root(mk(a), X[L - 1], ylo, A);
+    Y[L] = f_of(X[L]);
+    ++L;
+  }
+  if (L != ZG_MZ_LAYERS) return ZG_EINVAL;
+  // region masses: the tail beyond X_0, and overhang k between X_k and
+  // X_{k-1} above Y_{k-1} (X_L = 0: the cap)
+  dd Xe[N + 1], Ye[N + 1], Fx[N + 1], a[N + 1];
+  for (int k = 0; k < L; ++k) {
+    Xe[k] = X[k];
+    Ye[k] = Y[k];
+    Fx[k] = F_of(X[k]);
+  }
+  Xe[L] = mk(0.0);
+  Ye[L] = one;
+  Fx[L] = mk(0.0);
+  a[0] = sub(T, Fx[0]);
+  dd S = a[0];
+  for (int k = 1; k <= L; ++k) {
+    a[k] = sub(sub(Fx[k - 1], Fx[k]), mul(Ye[k - 1], sub(Xe[k - 1], Xe[k])));
+    S = add(S, a[k]);
+  }
+  // the layers and the regions make up the whole mass
+  const dd close = sub(add(mul(A, mk((double)L)), S), T);
+  if (!(std::fabs(close.hi) < 1e-28)) return ZG_EINVAL;
+  // integer masses in units of 2^-63 of a bucket, summing to N buckets
+  using u128 = unsigned __int128;
+  const u128 UNIT = (u128)1 << 63, TOTAL = (u128)N << 63;
+  u128 m[N] = {};
+  u128 sum = 0;
+  int big = 0;
+  for (int k = 0; k <= L; ++k) {
+    m[k] = nint_u128(mul_pow2(divide(a[k], S), 0x1p71));
+    sum += m[k];
+    if (m[k] > m[big]) big = k;
+  }
+  m[big] = m[big] + TOTAL - sum;
+  const std::vector<u128> mass(m, m + N);
+  // alias table: the lowest-index bucket below one unit takes the rest of
+  // its unit from the lowest-index bucket above
+  std::set<int> small;
+  std::deque<int> large;
+  for (int j = 0; j < N; ++j) {
+    t->thr[j] = (uint64_t)UNIT;
+    t->alias[j] = (uint8_t)j;
+    if (m[j] < UNIT)
+      small.insert(j);
+    else if (m[j] > UNIT)
+      large.push_back(j);
+  }
+  while (!small.empty() && !large.empty()) {
+    const int j = *small.begin();
+    small.erase(small.begin());
+    const int l = large.front();
+    t->thr[j] = (uint64_t)m[j];
+    t->alias[j] = (uint8_t)l;
+    m[l] -= UNIT - m[j];
+    if (m[l] < UNIT) {
+      large.pop_front();
+      small.insert(l);
+    } else if (m[l] == UNIT) {
+      large.pop_front();
+    }
+  }
+  // the table gives every region its integer mass back
+  std::vector<u128> got(N, 0);
+  for (int j = 0; j < N; ++j) {
+    got[j] += t->thr[j];
+    got[t->alias[j]] += UNIT - t->thr[j];
+  }
+  if (got != mass) return ZG_EINVAL;
+  t->x0 = rn64(X[0]);
+  for (int i = 0; i < L; ++i) t->xs[i] = rn64(X[i]) * 0x1p-63;
+  for (int k = 1; k <= L; ++k) {
+    t->ox[k] = rn64(Xe[k - 1]);
+    t->odx[k] = rn64(sub(Xe[k - 1], Xe[k]));
+    t->oy[k] = rn64(Ye[k - 1]);
+    t->ody[k] = rn64(sub(Ye[k], Ye[k - 1]));
+    t->kind[k] = !lt(Xe[k], one) ? 1 : (!lt(one, Xe[k - 1]) ? 2 : 3);
+  }
+  return ZG_OK;
+}
 
 zg_status build_table(zg_table_view *t) {
   // bisection for r on [0.5, 5]: 110 halvings reach double-double resolution
@@ -265,7 +427,45 @@ void build_lcg_tables(LcgTables *L) {
 
 }  // namespace zg
 
+namespace zg {
+
+zg_status build_dev_tables(const zg_table_view &tv, DevTables *h) {
+  std::memset(h, 0, sizeof(*h));
+  for (int i = 0; i < ZG_LAYERS; ++i) {
+    h->fast64[i] = {tv.k53[i], tv.w53[i]};
+    h->fast32[i] = {tv.k24[i], tv.w24[i]};
+    h->y[i] = tv.y[i];
+    h->dy[i] = tv.dy[i];
+    h->w53[i] = tv.w53[i];
+    h->w24d[i] = tv.w24d[i];
+  }
+  h->r = tv.r;
+  zg_mz_table_view mzv;
+  const zg_status st = build_mz_table(&mzv);
+  if (st != ZG_OK) return st;
+  MzTabs &M = h->mz;
+  for (int i = 0; i < ZG_MZ_BUCKETS; ++i) {
+    M.xs[i] = mzv.xs[i];
+    M.bucket[i] = {mzv.thr[i], mzv.alias[i], 0};
+  }
+  for (int k = 0; k <= ZG_MZ_LAYERS; ++k) {
+    M.region[k] = {mzv.ox[k], mzv.odx[k], mzv.oy[k], mzv.ody[k]};
+    M.kind[k] = mzv.kind[k];
+  }
+  M.x0 = mzv.x0;
+  build_lcg_tables(&h->lcg);
+  build_log_tables(&h->logt);
+  return ZG_OK;
+}
+
+}  // namespace zg
+
 extern "C" zg_status zg_build_table(zg_table_view *out) {
   if (!out) return ZG_EINVAL;
   return zg::build_table(out);
+}
+
+extern "C" zg_status zg_build_mz_table(zg_mz_table_view *out) {
+  if (!out) return ZG_EINVAL;
+  return zg::build_mz_table(out);
 }

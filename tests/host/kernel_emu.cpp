@@ -137,18 +137,10 @@ static DevTables *host_tables() {
   zg_table_view tv;
   if (build_table(&tv) != ZG_OK) return nullptr;
   DevTables *T = new DevTables();
-  std::memset(T, 0, sizeof(*T));
-  for (int i = 0; i < ZG_LAYERS; ++i) {
-    T->fast64[i] = {tv.k53[i], tv.w53[i]};
-    T->fast32[i] = {tv.k24[i], tv.w24[i]};
-    T->y[i] = tv.y[i];
-    T->dy[i] = tv.dy[i];
-    T->w53[i] = tv.w53[i];
-    T->w24d[i] = tv.w24d[i];
+  if (build_dev_tables(tv, T) != ZG_OK) {
+    delete T;
+    return nullptr;
   }
-  T->r = tv.r;
-  build_lcg_tables(&T->lcg);
-  build_log_tables(&T->logt);
   return T;
 }
 

@@ -2,7 +2,8 @@
 stand-in (tests/host/shim) and AddressSanitizer, run through launch_fill:
 the wave-specialised kernel (streaming waves publishing slow elements in an
 LDS ring, drain waves resolving them) and the block-pooled kernel give every
-element bit for bit as the oracle does, for FP64, FP32 and mutation, both
+element bit for bit as the oracle does, for FP64, FP32, mutation and the
+modified ziggurat, both
 uniform kinds, unaligned heads, multi-stream jobs with ragged streams, tiny
 jobs and a job whose slow elements wrap the ring several times; no access
 leaves its buffer and every wave leaves its loops.  The workgroups of a grid
@@ -26,7 +27,7 @@ def emu(tmp_path_factory):
     return d, exe
 
 
-# op (0 FP64, 1 FP32, 3 mutation), kind, seed, s0, n_streams, n_per, first, head,
+# op (0 FP64, 1 FP32, 3 mutation, 4 modified ziggurat), kind, seed, s0, n_streams, n_per, first, head,
 # drain waves (0 = pooled kernel), steps per group, compute units (persistent
 # workgroups)
 CASES = [
@@ -43,13 +44,20 @@ CASES = [
     (0, 1, 99, 17, 701, 333, 5, 1, 0, 2, 3),
     (1, 1, 8, 0, 4001, 37, 0, 1, 0, 8, 4),
     (0, 2, 77, 1, 3, 50001, 9, 1, 0, 1, 2),
+    (4, 1, 7, 0, 1, 262144 + 37, 0, 1, 4, 4, 4),
+    (4, 1, 99, 17, 701, 333, 5, 0, 2, 8, 3),
+    (4, 2, 123456789, 3, 1, 100003, 1000, 1, 1, 2, 2),
+    (4, 1, 5, 2, 1, 1, 0, 1, 4, 4, 4),
+    (4, 1, 99, 17, 701, 333, 5, 1, 0, 2, 3),
+    (4, 2, 77, 1, 3, 50001, 9, 1, 0, 1, 2),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[
     "f64-sm64-ragged", "f64-multistream", "f64-lcg", "f32-multistream", "f32-lcg", "mutate",
     "f64-tiny", "f64-one", "f32-three", "f64-ring-wraps", "pooled-f64", "pooled-f32",
-    "pooled-lcg-one-step"])
+    "pooled-lcg-one-step", "mz-sm64", "mz-multistream", "mz-lcg", "mz-one", "mz-pooled",
+    "mz-pooled-lcg"])
 def test_fill_kernels_equal_oracle(emu, orc, case):
     op, kind, seed, s0, ns, n_per, first, head, drain, gsteps, cus = case
     d, exe = emu
@@ -75,6 +83,9 @@ def test_fill_kernels_equal_oracle(emu, orc, case):
     elif op == 3:
         got = np.fromfile(out, dtype=np.float64)
         want, _cls, errs = orc.mutate(x0, kind, seed, s0, first, 0.1)
+    elif op == 4:
+        got = np.fromfile(out, dtype=np.float64)
+        want, _cls, errs = orc.fill_streams_mz(kind, seed, s0, ns, first, n_per)
     else:
         got = np.fromfile(out, dtype=np.float64)
         want, _cls, errs = orc.fill_streams_f64(kind, seed, s0, ns, first, n_per)
