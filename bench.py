@@ -330,6 +330,11 @@ def main():
         print(json.dumps({"c4_batch": row}), flush=True)
         return
     tune = ctx.zg_get_tune(Z.ZG_TUNE_FILL_F64)
+
+    def launch_of(t):
+        return {"kernel": "wave-specialised" if t[4] else "block-pooled", "tile": t[0],
+                "waves_per_block": t[1], "persistent_blocks_per_cu": t[2], "drain_waves": t[4],
+                "group_steps": t[5], "autotuned": bool(args.autotune)}
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     out.zero_()
 
@@ -366,7 +371,10 @@ def main():
     med, ci = median_ci(all_ms)
     bytes_per = 8.0 * n
     achieved = bytes_per / (ms * 1e-3) / 1e9
-    kernel = {"zig": "k_zig<OP_ZIG64>", "mz": "k_zig<OP_MZ64>", "polar": "k_polar"}[main_key]
+    mz_tune = ctx.zg_get_tune(Z.ZG_TUNE_FILL_MZ)
+    kname = lambda t, op: ("k_zigws" if t[4] else "k_zig") + f"<{op}>"
+    kernel = {"zig": kname(tune, "OP_ZIG64"), "mz": kname(mz_tune, "OP_MZ64"),
+              "polar": "k_polar"}[main_key]
     traffic = read_traffic(kernel)
     line = {
         "metric": METRIC,
@@ -389,10 +397,7 @@ def main():
                                "polar fill of the same shape timed beside it",
                    "method": {"zig": "ziggurat", "mz": "modified ziggurat",
                               "polar": "polar"}[main_key],
-                   "launch": {"kernel": "wave-specialised" if tune[4] else "block-pooled",
-                              "tile": tune[0], "waves_per_block": tune[1],
-                              "persistent_blocks_per_cu": tune[2], "drain_waves": tune[4],
-                              "group_steps": tune[5], "autotuned": bool(args.autotune)},
+                   "launch": launch_of(tune),
                    "variates_per_step": n, "streams": N_STREAMS, "per_stream": N_PER},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -422,10 +427,11 @@ def main():
                         "65536 streams x 4096 (the same buffer and launch shape)",
             "value": n / (mwall * 1e-3), "unit": "variates/s", "ms_per_step": mwall,
             "kernel_ms": mms, "kernel_ms_median": median_ci(res["mz"][1])[0],
+            "launch": launch_of(mz_tune),
             "ziggurat_over_mcfarland_kernel_time": ms / mms,
             "roofline": {"bound": "hbm", "achieved": mach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": mach / HBM_PEAK_GBS, "kernel": "k_zig<OP_MZ64>",
-                         "traffic": read_traffic("k_zig<OP_MZ64>")}}
+                         "frac": mach / HBM_PEAK_GBS, "kernel": kname(mz_tune, "OP_MZ64"),
+                         "traffic": read_traffic(kname(mz_tune, "OP_MZ64"))}}
     del out
     torch.cuda.empty_cache()
     if not args.no_extra:

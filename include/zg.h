@@ -403,13 +403,15 @@ typedef struct zg_tune {
 #define ZG_TUNE_POLAR 2
 #define ZG_TUNE_MUTATE 3
 #define ZG_TUNE_BATCH 4
-#define ZG_TUNE_CLASSES 5
+#define ZG_TUNE_FILL_MZ 5   /* the modified ziggurat's plain fills */
+#define ZG_TUNE_CLASSES 6
 zg_status zg_get_tune(const zg_ctx *ctx, int cls, zg_tune *out);
 zg_status zg_set_tune(zg_ctx *ctx, int cls, const zg_tune *in);
 /* Times each candidate shape for each class on a scratch buffer of `bytes`
  * (0 = 1 GiB) and keeps the fastest; writes/reads a JSON cache at cache_path
  * (NULL: no cache).  When use_cache != 0 and the cache has an entry for this
- * device, nothing is timed. */
+ * device, nothing is timed.  The modified ziggurat's class keeps its current
+ * shape (it is not timed). */
 zg_status zg_autotune(zg_ctx *ctx, const char *cache_path, uint64_t bytes, int use_cache);
 
 /* ---------------------------------------------------------------- serving */

@@ -45,7 +45,8 @@ ZG_OP_FILL = 0
 ZG_OP_MUTATE = 1
 ZG_NO_HANDLE = -1
 ZG_MAX_BATCH = 32768
-ZG_TUNE_FILL_F64, ZG_TUNE_FILL_F32, ZG_TUNE_POLAR, ZG_TUNE_MUTATE, ZG_TUNE_BATCH = range(5)
+ZG_TUNE_FILL_F64, ZG_TUNE_FILL_F32, ZG_TUNE_POLAR, ZG_TUNE_MUTATE, ZG_TUNE_BATCH, ZG_TUNE_FILL_MZ = range(6)
+ZG_TUNE_CLASSES = 6
 ZG_SERVE_BATCHED = 0
 ZG_SERVE_PER_REQUEST = 1
 ZG_SM64_WINDOW = 1 << 40

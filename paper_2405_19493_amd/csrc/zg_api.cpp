@@ -19,19 +19,22 @@ using namespace zg;
 namespace {
 
 const zg_tune DEFAULT_TUNE[ZG_TUNE_CLASSES] = {
-    {1024, 16, 2, 0, 0, 4},   // FILL_F64: pooled, persistent, at most 2 workgroups per CU
-    {4096, 16, 2, 0, 0, 4},   // FILL_F32
+    // plain fills: the fastest shapes of a sweep of both kernels on 2^28
+    // variates, 65536 streams x 4096 (drain_waves > 0: wave-specialised)
+    {1024, 16, 2, 0, 4, 2},   // FILL_F64: wave-specialised, 4 drain waves, 2 steps per group
+    {4096, 16, 2, 0, 3, 4},   // FILL_F32: wave-specialised, 3 drain waves
     {2048, 8, 0, 0, 0, 4},    // POLAR
     {2048, 16, 2, 0, 4, 4},   // MUTATE: wave-specialised, 4 drain waves
     {2048, 8, 4, 0, 0, 4},    // BATCH (k_batch is bounded to 512 threads)
+    {2048, 16, 2, 0, 0, 4},   // FILL_MZ: block-pooled, persistent, 2048 x 16 tiles
 };
 
 uint32_t chunk_of(uint32_t op) { return op == OP_ZIG32 ? 256u : 128u; }
 
 int tune_class(uint32_t op) {
   switch (op) {
-    case OP_ZIG64:
-    case OP_MZ64: return ZG_TUNE_FILL_F64;
+    case OP_ZIG64: return ZG_TUNE_FILL_F64;
+    case OP_MZ64: return ZG_TUNE_FILL_MZ;
     case OP_ZIG32: return ZG_TUNE_FILL_F32;
     case OP_POLAR: return ZG_TUNE_POLAR;
     default: return ZG_TUNE_MUTATE;

@@ -1430,6 +1430,12 @@ __global__ __launch_bounds__(1024) void k_zigws(Job J, const DevTables *__restri
     const LaneConst LC = lane_constants<OP, KIND>(T);
     ws_stream<OP, KIND>(J, L, T, LC, head, J.n_total, gsteps);
   } else {
+    // The drain waves share each SIMD with streaming waves.  At equal issue
+    // priority their long dependent chains (hashes, exp, log) fall behind
+    // the slow elements the streaming waves publish, the ring fills and the
+    // streaming waves wait on it; one step of priority keeps the drain ahead
+    // (the streaming waves still fill the store pipe).
+    __builtin_amdgcn_s_setprio(1);
     ws_drain<OP, KIND>(J, L, T, r, dmax, n_stream, wave - n_stream, budget);
   }
   __syncthreads();

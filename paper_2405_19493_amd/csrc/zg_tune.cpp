@@ -21,7 +21,8 @@ using namespace zg;
 
 namespace {
 
-const char *CLASS_NAME[ZG_TUNE_CLASSES] = {"fill_f64", "fill_f32", "polar", "mutate", "batch"};
+const char *CLASS_NAME[ZG_TUNE_CLASSES] = {"fill_f64", "fill_f32", "polar",
+                                          "mutate",   "batch",    "fill_mz"};
 
 bool read_cache(const char *path, const std::string &arch, zg_tune *out) {
   FILE *f = std::fopen(path, "r");
@@ -120,7 +121,8 @@ extern "C" zg_status zg_autotune(zg_ctx *ctx, const char *cache_path, uint64_t b
         for (uint32_t gs : {2u, 4u}) cands.push_back({tl, w, res, 0, 0, gs});
   for (uint32_t dw : {3u, 4u, 6u, 8u})
     for (uint32_t gs : {2u, 4u, 8u}) cands.push_back({1024, 16, 2, 0, dw, gs});
-  for (int c = 0; c < ZG_TUNE_CLASSES - 1 && st == ZG_OK; ++c) {
+  // the plain-fill classes (the batch below; the modified ziggurat keeps its shape)
+  for (int c = 0; c < ZG_TUNE_BATCH && st == ZG_OK; ++c) {
     zg_tune best = ctx->tune[c];
     float best_ms = 1e30f;
     for (const zg_tune &base : cands) {

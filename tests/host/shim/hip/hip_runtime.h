@@ -108,6 +108,7 @@ inline uint32_t atomicCAS(uint32_t *p, uint32_t cmp, uint32_t val) {
 #define __hip_atomic_load(p, o, s) __atomic_load_n(p, __ATOMIC_SEQ_CST)
 #define __builtin_amdgcn_fence(o, s) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
+#define __builtin_amdgcn_s_setprio(n) ((void)0)
 
 inline double __longlong_as_double(long long x) { double d; std::memcpy(&d, &x, 8); return d; }
 inline long long __double_as_longlong(double x) { long long d; std::memcpy(&d, &x, 8); return d; }

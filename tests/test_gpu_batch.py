@@ -71,7 +71,7 @@ def test_batch_equals_plain_calls_and_shapes(ctx, zg):
     reqs = _uneven_requests(120, rng, max_log2=15, with_mutate=False)
     ctx.zg_batch(reqs)
     ref = [host(r["out"]).copy() for r in reqs]
-    saved = {c: ctx.zg_get_tune(c) for c in range(5)}
+    saved = {c: ctx.zg_get_tune(c) for c in range(zg.ZG_TUNE_CLASSES)}
     try:
         shapes = [(1024, 4, 1), (2048, 8, 2), (4096, 16, 4), (8192, 2, 1)]
         for tile, waves, bpc in shapes:

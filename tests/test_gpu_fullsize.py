@@ -46,14 +46,17 @@ def _oracle_at(kind, seed, positions, n_per, method=0):
     return vals, cls
 
 
-def test_c2_full_parity_ziggurat(ctx, zg):
+@pytest.mark.parametrize("shape", ["default", "pooled"])
+def test_c2_full_parity_ziggurat(ctx, zg, shape):
     """Every one of the 2^28 FP64 ziggurat variates of the benchmark's workload
-    against the oracle (its multi-stream routine on the host's cores), with the
-    launch shape the benchmark's autotuner picks on MI355X: workgroup tiles of
-    1024 x 16 waves, at most 2 persistent workgroups per CU."""
+    against the oracle (its multi-stream routine on the host's cores), in the
+    library's default launch shape, the one the benchmark times (the
+    wave-specialised kernel), and in the block-pooled kernel at workgroup
+    tiles of 1024 x 16 waves, at most 2 persistent workgroups per CU."""
     n = N_STREAMS * N_PER
     before = ctx.zg_get_tune(zg.ZG_TUNE_FILL_F64)
-    ctx.zg_set_tune(zg.ZG_TUNE_FILL_F64, 1024, 16, 2)
+    if shape == "pooled":
+        ctx.zg_set_tune(zg.ZG_TUNE_FILL_F64, 1024, 16, 2, 0, 0, 4)
     try:
         out = torch.empty(n, dtype=torch.float64, device="cuda")
         ctx.zg_fill_streams(out, N_PER, N_STREAMS, kind=zg.ZG_SPLITMIX64, seed=7)

@@ -86,13 +86,13 @@ def test_mz_launch_shapes_same_bits(ctx, zg, kind):
     tiles, 1 to 8 steps per group) and wave-specialised (1 to 8 drain waves)
     launches of the modified ziggurat: the same bits, equal to the oracle."""
     n_per, ns = 777, 240   # streams 7..246: within the LCG's 256
-    saved = ctx.zg_get_tune(zg.ZG_TUNE_FILL_F64)
+    saved = ctx.zg_get_tune(zg.ZG_TUNE_FILL_MZ)
     try:
         ref = None
         for tile, waves, res, dw, gs in [(1024, 16, 2, 0, 4), (256, 4, 0, 0, 1), (512, 8, 1, 0, 8),
                                          (4096, 16, 0, 0, 2), (1024, 16, 2, 1, 4),
                                          (1024, 16, 2, 4, 2), (1024, 16, 2, 8, 8)]:
-            ctx.zg_set_tune(zg.ZG_TUNE_FILL_F64, tile, waves, res, 0, dw, gs)
+            ctx.zg_set_tune(zg.ZG_TUNE_FILL_MZ, tile, waves, res, 0, dw, gs)
             out = dev_empty(n_per * ns, torch.float64, 1)
             ctx.zg_fill_streams(out, n_per, ns, method=zg.ZG_MCFARLAND, kind=kind, seed=2,
                                 stream0=7, first_index=33)
@@ -103,16 +103,16 @@ def test_mz_launch_shapes_same_bits(ctx, zg, kind):
                 compare(got, want, cls, ("mz shapes", kind))
             assert got.tobytes() == ref, (tile, waves, res, dw, gs)
     finally:
-        ctx.zg_set_tune(zg.ZG_TUNE_FILL_F64, *saved)
+        ctx.zg_set_tune(zg.ZG_TUNE_FILL_MZ, *saved)
 
 
 @pytest.mark.parametrize("qcap", [1, 16])
 def test_mz_queue_overflow(ctx, zg, qcap):
-    saved = ctx.zg_get_tune(zg.ZG_TUNE_FILL_F64)
+    saved = ctx.zg_get_tune(zg.ZG_TUNE_FILL_MZ)
     try:
         outs = []
         for cap in (0, qcap):
-            ctx.zg_set_tune(zg.ZG_TUNE_FILL_F64, saved[0], saved[1], saved[2], cap)
+            ctx.zg_set_tune(zg.ZG_TUNE_FILL_MZ, saved[0], saved[1], saved[2], cap)
             out = dev_empty(100003, torch.float64, 1)
             ctx.zg_fill(out, method=zg.ZG_MCFARLAND, kind=1, seed=5, stream=2, first_index=7)
             outs.append(host(out).copy())
@@ -120,7 +120,7 @@ def test_mz_queue_overflow(ctx, zg, qcap):
         want, cls, _ = orc.fill_mz(1, 5, 2, 7, 100003)
         compare(outs[1], want, cls, ("mz overflow", qcap))
     finally:
-        ctx.zg_set_tune(zg.ZG_TUNE_FILL_F64, *saved)
+        ctx.zg_set_tune(zg.ZG_TUNE_FILL_MZ, *saved)
 
 
 @pytest.mark.parametrize("dmax", [1, 2, 3, 4, 5])
@@ -145,7 +145,7 @@ def test_mz_budget(ctx, zg, dmax):
 def test_mz_full_parity_2p28(ctx, zg):
     """Every one of the 2^28 variates of the benchmark's modified-ziggurat row
     (65536 streams x 4096, SplitMix64 seed 7) against the oracle, in the
-    library's default FP64 launch shape (the one the benchmark times), and
+    library's default launch shape for it (the one the benchmark times), and
     their statistics: moments, KS on a 1e7 subsample, the tail frequency
     erfc(X_0/sqrt 2)."""
     n = N_STREAMS * N_PER

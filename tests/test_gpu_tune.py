@@ -33,13 +33,13 @@ def _fills(ctx, zg):
 
 
 def test_autotune_shapes_keep_bits_and_cache(ctx, zg, tmp_path):
-    saved = {c: ctx.zg_get_tune(c) for c in range(5)}
+    saved = {c: ctx.zg_get_tune(c) for c in range(zg.ZG_TUNE_CLASSES)}
     try:
         ref = _fills(ctx, zg)
         cache = str(tmp_path / "tune.json")
         print("autotune on 64 MiB", flush=True)
         ctx.zg_autotune(cache, 64 << 20, use_cache=False)
-        tuned = {c: ctx.zg_get_tune(c) for c in range(5)}
+        tuned = {c: ctx.zg_get_tune(c) for c in range(zg.ZG_TUNE_CLASSES)}
         for c, (tile, waves, bpc, qcap, dw, gs) in tuned.items():
             assert qcap == 0 and gs in (1, 2, 4, 8) and 0 <= dw <= 8, (c, tuned[c])
             if dw == 0:
@@ -54,7 +54,7 @@ def test_autotune_shapes_keep_bits_and_cache(ctx, zg, tmp_path):
         for c, t in saved.items():
             ctx.zg_set_tune(c, *t)
         ctx.zg_autotune(cache, 64 << 20, use_cache=True)
-        assert {c: ctx.zg_get_tune(c) for c in range(5)} == tuned
+        assert {c: ctx.zg_get_tune(c) for c in range(zg.ZG_TUNE_CLASSES)} == tuned
     finally:
         for c, t in saved.items():
             ctx.zg_set_tune(c, *t)
