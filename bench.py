@@ -33,10 +33,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="approximate CPU work of the oracle baseline sample")
-    p.add_argument("--only", choices=["zig", "polar", "mz", "c4", "all"], default="all",
+    p.add_argument("--only", choices=["zig", "polar", "mz", "f32", "lcg", "mutate", "c4", "all"],
+                   default="all",
                    help="restrict the timed kernels (for profiling runs; c4: only the batch row, "
                         "printed as its own JSON line)")
-    p.add_argument("--serve-seconds", type=float, default=5.0,
+    p.add_argument("--serve-seconds", type=float, default=60.0,
                    help="serving-loop run per mode (open-loop Poisson, 20k requests/s); 0 = skip")
     p.add_argument("--autotune", action="store_true",
                    help="run the launch-shape autotuner (zg_autotune) first; by default the "
@@ -81,6 +82,22 @@ def time_kernel(fn, steps, warmup, torch):
     return sum(ms) / len(ms), ms, wall
 
 
+def time_kernel_back_to_back(fn, launches, warmup, torch):
+    """Average ms per launch of `launches` launches between one pair of HIP
+    events: for kernels of tens of microseconds, where events around every
+    launch would also time the host's launch gap."""
+    for _ in range(warmup):
+        fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(launches):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / launches
+
+
 def median_ci(xs, z=3.29):
     """Median of the per-launch times and a distribution-free 99.9% confidence
     interval for it (order statistics at n/2 -+ z sqrt(n)/2)."""
@@ -91,6 +108,11 @@ def median_ci(xs, z=3.29):
     lo = max(0, int(n / 2.0 - half))
     hi = min(n - 1, int(n / 2.0 + half + 0.999))
     return med, [v[lo], v[hi]]
+
+
+def note(msg):
+    """A progress line on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(seconds):
@@ -123,14 +145,23 @@ def cpu_baseline(seconds):
         one(k)
         k += 1
     dt1 = time.perf_counter() - t1
-    model = ""
+    cpu = {}
     try:
         with open("/proc/cpuinfo") as fh:
-            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+            for line in fh:
+                if ":" in line:
+                    key, val = (x.strip() for x in line.split(":", 1))
+                    if key in ("model name", "cpu family", "model", "stepping", "cpu MHz",
+                               "cache size") and key not in cpu:
+                        cpu[key] = val
     except OSError:
         pass
     return {"value": done / dt, "unit": "variates/s", "cores": cores, "kind": "oracle",
-            "cpu": model,
+            "cpu": cpu.get("model name", ""), "cpu_id": cpu,
+            "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "threads_note": "the oracle's threads are capped at 16, the host CPU share of one "
+                            "GPU on these machines, whatever nproc shows",
             "sample": f"streams 0..{s - 1} of the 65536 x 4096 FP64 ziggurat variates "
                       f"(SplitMix64 seed 7): {done} variates in {dt:.1f} s",
             "one_core": {"value": k * N_PER / dt1, "unit": "variates/s",
@@ -148,11 +179,14 @@ def c3_lcg(ctx, Z, torch, steps, warmup):
 
     ms, _, _ = time_kernel(go, steps, warmup, torch)
     del out
+    t = ctx.zg_get_tune(Z.ZG_TUNE_FILL_F64)
+    kernel = ("k_zigws" if t[4] else "k_zig") + "<OP_ZIG64, LCG48>"
     return {"workload": "ziggurat fill, 2^28 FP64, LCG48 seed 123456789, stream 0",
             "value": n / (ms * 1e-3), "unit": "variates/s", "kernel_ms": ms,
             "roofline": {"bound": "hbm", "achieved": 8.0 * n / (ms * 1e-3) / 1e9,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": 8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+                         "frac": 8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "kernel": kernel, "traffic": read_traffic(kernel)}}
 
 
 def sequential_row(ctx, Z, torch, steps, warmup):
@@ -192,10 +226,13 @@ def f32_row(ctx, Z, torch, steps, warmup):
     ms, _, _ = time_kernel(go, steps, warmup, torch)
     del out
     gbs = 4.0 * n / (ms * 1e-3) / 1e9
+    t = ctx.zg_get_tune(Z.ZG_TUNE_FILL_F32)
+    kernel = ("k_zigws" if t[4] else "k_zig") + "<OP_ZIG32>"
     return {"workload": "ziggurat fill, 2^28 FP32, SplitMix64 seed 7, 65536 streams x 4096",
             "value": n / (ms * 1e-3), "unit": "variates/s", "kernel_ms": ms,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS}}
+                         "frac": gbs / HBM_PEAK_GBS, "kernel": kernel,
+                         "traffic": read_traffic(kernel)}}
 
 
 def c4_recipe():
@@ -251,13 +288,18 @@ def c4_batch(ctx, Z, torch, reps):
         ctx.zg_fill_each(creqs)
 
     variates = int(sizes.sum()) + genes
+    total_bytes = int(sum(nbytes)) + 16 * genes   # outputs written, genes read and written
     out = {"workload": "10^4 requests, sizes clamp(2^(20u),1,2^20), 70% FP64 / 30% FP32, "
                        "plus a 4096x1024-gene mutation (sigma 0.1)", "variates": variates,
            "per_request_form": "zg_fill_each: one plain launch per request, from a C loop"}
     kept = None
     same = True
     for name, fn in (("batched", batched), ("per_request", plain)):
+        # one call at a time (the latency of one call, host planning included),
+        # and calls back to back (the throughput of a stream of such calls: the
+        # host plans the next while the device runs this one)
         ms, _, _ = time_kernel(fn, reps, 1, torch)
+        ms_b2b = time_kernel_back_to_back(fn, 2 * reps, 0, torch)
         pool[:g0].zero_()
         fn()
         torch.cuda.synchronize()
@@ -266,19 +308,60 @@ def c4_batch(ctx, Z, torch, reps):
         else:
             # every byte of every request and of the mutated genes
             same = bool(torch.equal(kept, pool[:g0 + genes * 8]))
-        out[name] = {"ms": ms, "variates_per_s": variates / (ms * 1e-3)}
+        out[name] = {"ms": ms, "variates_per_s": variates / (ms * 1e-3),
+                     "ms_back_to_back": ms_b2b,
+                     "variates_per_s_back_to_back": variates / (ms_b2b * 1e-3),
+                     "bytes_per_s_back_to_back": total_bytes / (ms_b2b * 1e-3)}
     del kept
     out["same_bits"] = same
     out["speedup"] = out["per_request"]["ms"] / out["batched"]["ms"]
-    # the mutation row alone, against its own roofline (8 B read + 8 B written per gene)
-    ms, _, _ = time_kernel(lambda: ctx.zg_mutate(x, 0.1, seed=999, stream=0), 20, 3, torch)
-    out["mutation"] = {"genes": genes, "kernel_ms": ms, "genes_per_s": genes / (ms * 1e-3),
-                       "roofline": {"bound": "hbm", "achieved": 16.0 * genes / (ms * 1e-3) / 1e9,
-                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                    "frac": 16.0 * genes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    out["speedup_back_to_back"] = (out["per_request"]["ms_back_to_back"] /
+                                   out["batched"]["ms_back_to_back"])
+    out["mutation"] = mutation_row(ctx, torch, x, 20, 3)
     del pool, views, x, x0
     torch.cuda.empty_cache()
     return out
+
+
+def mutation_row(ctx, torch, x, steps, warmup):
+    """The c4 mutation alone (4096 x 1024 genes, sigma 0.1, seed 999), against
+    its own roofline: 8 B read + 8 B written per gene."""
+    genes = x.numel()
+    ms = time_kernel_back_to_back(lambda: ctx.zg_mutate(x, 0.1, seed=999, stream=0),
+                                  max(steps, 50), warmup, torch)
+    gbs = 16.0 * genes / (ms * 1e-3) / 1e9
+    t = ctx.zg_get_tune(3)
+    kernel = ("k_zigws" if t[4] else "k_zig") + "<OP_MUTATE>"
+    return {"genes": genes, "kernel_ms": ms, "timing": "back-to-back launches between two events",
+            "genes_per_s": genes / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "kernel": kernel,
+                         "traffic": read_traffic(kernel)}}
+
+
+def read_profile(kernel):
+    """The committed rocprofv3 summary entry of a kernel (profiles/traffic.json),
+    if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            ent = json.load(fh).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not ent:
+        return None
+    import hashlib
+    src = os.path.join(ROOT, "paper_2405_19493_amd", "csrc", "zg_kernels.hip")
+    with open(src, "rb") as fh:
+        if ent.get("source_sha") != hashlib.sha256(fh.read()).hexdigest()[:16]:
+            return None
+    return ent
+
+
+# VALU issue peak: one wave-64 instruction per 4 cycles per SIMD (a 16-lane
+# SIMD; FP64 and 64-bit integer work, the bulk of these kernels, run at that
+# rate), 256 CUs x 4 SIMDs at 2.4 GHz
+VALU_PEAK_G = 256 * 4 * 2.4e9 / 4 / 1e9
 
 
 def read_traffic(kernel):
@@ -323,6 +406,20 @@ def main():
         import tempfile
         cache = os.path.join(tempfile.gettempdir(), "zg_autotune_2p28.json")
         ctx.zg_autotune(cache, 8 * N_STREAMS * N_PER, use_cache=True)
+    if args.only in ("f32", "lcg", "mutate"):
+        # one row alone (short runs under a profiler)
+        if args.only == "f32":
+            row = f32_row(ctx, Z, torch, args.steps, args.warmup)
+        elif args.only == "lcg":
+            row = c3_lcg(ctx, Z, torch, args.steps, args.warmup)
+        else:
+            import numpy as np
+            rng = np.random.Generator(np.random.PCG64(5))
+            x = torch.from_numpy(rng.uniform(-5.0, 5.0, 4096 * 1024)).cuda()
+            row = mutation_row(ctx, torch, x, args.steps, args.warmup)
+        ctx.close()
+        print(json.dumps({args.only: row}), flush=True)
+        return
     if args.only == "c4":
         row = c4_batch(ctx, Z, torch, 3)
         row["batch_tune"] = list(ctx.zg_get_tune(Z.ZG_TUNE_BATCH))
@@ -356,6 +453,7 @@ def main():
         # write bandwidth this machine reaches with no compute at all
         res["store_only"] = time_kernel(lambda: out.fill_(0.5), args.steps, args.warmup, torch)
     if args.only in ("zig", "all"):
+        note("ziggurat fill, 2^28 FP64")
         res["zig"] = time_kernel(zig, args.steps, args.warmup, torch)
     if args.only in ("polar", "all"):
         res["polar"] = time_kernel(polar, args.steps, args.warmup, torch)
@@ -414,7 +512,17 @@ def main():
         line["polar"] = {"value": n / (pwall * 1e-3), "unit": "variates/s", "ms_per_step": pwall,
                          "kernel_ms": pms,
                          "roofline": {"bound": "hbm", "achieved": pach, "peak": HBM_PEAK_GBS,
-                                      "unit": "GB/s", "frac": pach / HBM_PEAK_GBS}}
+                                      "unit": "GB/s", "frac": pach / HBM_PEAK_GBS,
+                                      "kernel": "k_polar", "traffic": read_traffic("k_polar")}}
+        prof = read_profile("k_polar")
+        if prof:
+            # polar is bound by VALU issue: its instruction rate against that peak
+            rate = prof["valu_per_64"] * n / 64 / (pms * 1e-3) / 1e9
+            line["polar"]["alu_view"] = {
+                "bound": "alu", "achieved": rate, "peak": VALU_PEAK_G,
+                "unit": "G VALU wave-instructions/s", "frac": rate / VALU_PEAK_G,
+                "valu_per_64_variates": prof["valu_per_64"],
+                "source": "profiles/polar_2p28.counters.txt (SQ_INSTS_VALU)"}
     if "mz" in res and main_key == "zig":
         # the modified ziggurat (McFarland's method) on the same workload: the
         # paper's comparator, measured 11.52% faster than the original on
@@ -435,14 +543,17 @@ def main():
     del out
     torch.cuda.empty_cache()
     if not args.no_extra:
+        note("FP32, LCG, sequential and c4 rows")
         line["f32"] = f32_row(ctx, Z, torch, args.steps, args.warmup)
         line["c3_lcg"] = c3_lcg(ctx, Z, torch, args.steps, args.warmup)
         line["sequential"] = sequential_row(ctx, Z, torch, args.steps, args.warmup)
         line["c4_batch"] = c4_batch(ctx, Z, torch, 3)
     if args.serve_seconds > 0:
         from paper_2405_19493_amd import serve_bench
+        note(f"serving, {args.serve_seconds:.0f} s per mode")
         line["serving"] = serve_bench.run(ctx, duration_s=args.serve_seconds)
     if not args.no_cpu_baseline:
+        note("CPU baseline (the oracle)")
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -14,6 +14,7 @@ The same arrival trace runs once in batched mode and once in per-request mode
 requests is then regenerated alone with zg_fill at the first index the server
 gave them, and must match bit for bit (alone-vs-mix).
 """
+import sys
 import threading
 import time
 
@@ -164,6 +165,8 @@ def run(ctx, duration_s=5.0, rate=20000.0, n_handles=65536, mem_cap=64 << 30, wi
         out["requests"] = len(trace[0])
         out["mean_request_variates"] = float(trace[1].mean()) if len(trace[0]) else 0.0
         for name, mode in modes:
+            print(f"serve: {name}, {duration_s:.0f} s at {rate:.0f} requests/s", file=sys.stderr,
+                  flush=True)
             out[name] = replay_mode(ctx, mode, trace, handles, mem_cap, window_us)
         # alone-vs-mix: a shorter trace driven from Python so outputs can be kept
         ctrace = make_trace(rate, check_s, n_handles, seed=6)
@@ -176,6 +179,7 @@ def run(ctx, duration_s=5.0, rate=20000.0, n_handles=65536, mem_cap=64 << 30, wi
                                                               lambda h: 1000 + h, lambda h: h)
             out[name]["errors"] = len(errors)
         rows = []
+        print("serve: rate sweep", file=sys.stderr, flush=True)
         for r in sweep:
             tr = make_trace(float(r), sweep_s, n_handles, seed=7)
             row = {"rate_per_s": r}
@@ -185,6 +189,11 @@ def run(ctx, duration_s=5.0, rate=20000.0, n_handles=65536, mem_cap=64 << 30, wi
                                                  "p99_latency_ms", "batches")}
             rows.append(row)
         out["sweep"] = rows
+        # the lowest offered rate of the sweep at which the batched mode's p99
+        # beats the per-request mode's (None: not within the sweep)
+        out["p99_crossover_rate_per_s"] = next(
+            (row["rate_per_s"] for row in rows
+             if row["batched"]["p99_latency_ms"] < row["per_request"]["p99_latency_ms"]), None)
     finally:
         for h in handles:
             ctx.zg_stream_close(h)
