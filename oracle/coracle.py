@@ -125,6 +125,9 @@ def lib():
         L.orc_mz_attempt.restype = i32
         L.orc_mz_enum.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.orc_mz_enum.restype = i32
+        L.orc_ea_step.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, u32, u64, u32, u64, u64,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, u32, i32]
+        L.orc_ea_step.restype = u64
         L.orc_fill_streams_mz.argtypes = [vp, i32, u64, u32, u32, u64, u64, u32, vp, vp, i32]
         L.orc_fill_streams_mz.restype = u64
         _lib = L
@@ -354,6 +357,28 @@ def fill_polar(kind, seed, s, first, n, dmax=DMAX, nthreads=0):
     errs = lib().orc_fill_polar(kind, seed & (2**64 - 1), s, first, n, dmax, _p(out),
                                 _p(cls), _threads(nthreads))
     return out, cls, int(errs)
+
+
+def ea_rate53(rate):
+    """The 53-bit mutation threshold of a per-gene rate: floor(rate 2^53),
+    clamped to [0, 2^53]."""
+    return max(0, min(1 << 53, int(float(rate) * 2.0 ** 53)))
+
+
+def ea_step(parents, fitness, k, seed, stream, gen, rate, sigma, lo, hi, dmax=DMAX,
+            nthreads=0, L=None):
+    """One EA generation (orc_ea_step): parents (pop x genes float64) and
+    fitness (pop) -> (children, winners, per-gene outcome codes, errors)."""
+    P = np.ascontiguousarray(parents, dtype=np.float64)
+    F = np.ascontiguousarray(fitness, dtype=np.float64)
+    pop, genes = P.shape
+    C = np.empty_like(P)
+    W = np.empty(pop, dtype=np.uint32)
+    cls = np.empty(P.shape, dtype=np.uint8)
+    errs = (L or lib()).orc_ea_step(ctypes.byref(table()), _p(P), _p(F), _p(C), _p(W), _p(cls),
+                                    pop, genes, k, seed & (2**64 - 1), stream, gen,
+                                    ea_rate53(rate), sigma, lo, hi, dmax, _threads(nthreads))
+    return C, W, cls, int(errs)
 
 
 def mutate(x, kind, seed, s, first, sigma, dmax=DMAX, nthreads=0):

@@ -850,6 +850,95 @@ uint64_t orc_mutate(const orc_table *T, int kind, uint64_t seed, uint32_t s, uin
   return run_split(j, n, nthreads);
 }
 
+/* ------------------------------------------------ one EA generation step */
+/*
+ * The fused consumer of Section 1's prior work (an evolutionary algorithm
+ * that ran 20-25% faster with the ziggurat), as read here: one generation
+ * of a population of `pop` genomes of `genes` doubles, minimising fitness.
+ *  - Child c (0 <= c < pop) of generation `gen` has the key u = gen pop + c.
+ *    Its parent wins a tournament of `k` draws with replacement: draw t
+ *    picks index floor(W(seed, stream, u, t) pop / 2^64), and the winner is
+ *    the first draw of least fitness: a later draw replaces the current best
+ *    when its fitness is strictly smaller, or when the best's is NaN and its
+ *    own is not (a NaN fitness wins only when every draw has one).
+ *  - Gene g of child c (key w = u genes + g) copies the winner's gene g; it
+ *    mutates iff (W(seed, stream + 1, w, 0) >> 11) < rate53, a 53-bit
+ *    threshold (the host rounds rate 2^53 down), by x += sigma z with z the
+ *    FP64 ziggurat variate w of stream stream + 2 (SplitMix64, the oracle's
+ *    own orc_zig_f64); then x is clamped to [lo, hi] (a NaN stays NaN).
+ * Outputs: children (pop x genes), winners (pop), cls per gene (255 for a
+ * copy, else the ziggurat's outcome code).  Returns the budget failures.
+ */
+typedef struct {
+  const orc_table *T;
+  const double *parents, *fitness;
+  double *children;
+  uint32_t *winners;
+  uint8_t *cls;
+  uint64_t seed, gen, rate53;
+  uint32_t pop, genes, k, stream, dmax;
+  double sigma, lo, hi;
+  uint32_t c0, c1;
+  uint64_t errors;
+} orc_ea_job;
+
+static uint32_t ea_draw(uint64_t W, uint32_t pop) {
+  return (uint32_t)(((unsigned __int128)W * pop) >> 64);
+}
+
+static void *run_ea(void *arg) {
+  orc_ea_job *J = (orc_ea_job *)arg;
+  for (uint32_t c = J->c0; c < J->c1; ++c) {
+    const uint64_t u = J->gen * J->pop + c;
+    uint32_t best = ea_draw(orc_sm64_word(J->seed, J->stream, u, 0), J->pop);
+    for (uint32_t t = 1; t < J->k; ++t) {
+      const uint32_t i = ea_draw(orc_sm64_word(J->seed, J->stream, u, t), J->pop);
+      const double fi = J->fitness[i], fb = J->fitness[best];
+      if (fi < fb || (isnan(fb) && !isnan(fi))) best = i;
+    }
+    if (J->winners) J->winners[c] = best;
+    for (uint32_t g = 0; g < J->genes; ++g) {
+      const uint64_t w = u * J->genes + g;
+      double x = J->parents[(uint64_t)best * J->genes + g];
+      uint8_t cl = 255;
+      if ((orc_sm64_word(J->seed, J->stream + 1, w, 0) >> 11) < J->rate53) {
+        const double z = orc_zig_f64(J->T, ORC_SM64, J->seed, J->stream + 2, w, J->dmax, &cl);
+        if ((cl & 3) == 3) J->errors++;
+        x = x + J->sigma * z;
+        x = x < J->lo ? J->lo : (x > J->hi ? J->hi : x);
+      }
+      J->children[(uint64_t)c * J->genes + g] = x;
+      if (J->cls) J->cls[(uint64_t)c * J->genes + g] = cl;
+    }
+  }
+  return 0;
+}
+
+uint64_t orc_ea_step(const orc_table *T, const double *parents, const double *fitness,
+                     double *children, uint32_t *winners, uint8_t *cls, uint32_t pop,
+                     uint32_t genes, uint32_t k, uint64_t seed, uint32_t stream, uint64_t gen,
+                     uint64_t rate53, double sigma, double lo, double hi, uint32_t dmax,
+                     int nthreads) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 64) nthreads = 64;
+  pthread_t th[64];
+  orc_ea_job jobs[64];
+  for (int t = 0; t < nthreads; ++t) {
+    orc_ea_job j = {T, parents, fitness, children, winners, cls, seed, gen, rate53,
+                    pop, genes, k, stream, dmax, sigma, lo, hi,
+                    (uint32_t)((uint64_t)pop * t / nthreads),
+                    (uint32_t)((uint64_t)pop * (t + 1) / nthreads), 0};
+    jobs[t] = j;
+    pthread_create(&th[t], 0, run_ea, &jobs[t]);
+  }
+  uint64_t errs = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    pthread_join(th[t], 0);
+    errs += jobs[t].errors;
+  }
+  return errs;
+}
+
 /* Raw words W(seed, s, first + k, d) for k < n. */
 void orc_words(int kind, uint64_t seed, uint32_t s, uint32_t d, uint64_t first, uint64_t n,
                uint64_t *out) {
