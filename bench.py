@@ -33,7 +33,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="approximate CPU work of the oracle baseline sample")
-    p.add_argument("--only", choices=["zig", "polar", "mz", "f32", "lcg", "mutate", "c4", "all"],
+    p.add_argument("--only", choices=["zig", "polar", "mz", "f32", "lcg", "mutate", "ea", "c4",
+                                      "all"],
                    default="all",
                    help="restrict the timed kernels (for profiling runs; c4: only the batch row, "
                         "printed as its own JSON line)")
@@ -339,6 +340,34 @@ def mutation_row(ctx, torch, x, steps, warmup):
                          "traffic": read_traffic(kernel)}}
 
 
+def ea_row(ctx, Z, torch, steps, warmup):
+    """One EA generation (zg_ea_step): 16384 genomes x 1024 genes, sphere
+    fitness, binary tournament, per-gene rate 0.05, sigma 0.1, bounds [-5, 5];
+    against the HBM roofline of 8 B read + 8 B written per gene."""
+    pop, genes = 16384, 1024
+    g = torch.Generator(device="cpu").manual_seed(7)
+    P = (torch.rand((pop, genes), generator=g, dtype=torch.float64) * 10.0 - 5.0).cuda()
+    F = (P * P).sum(dim=1)
+    C = torch.empty_like(P)
+    W = torch.empty(pop, dtype=torch.int32, device="cuda")
+
+    def go():
+        ctx.zg_ea_step(P, F, C, W, tournament=2, rate=0.05, sigma=0.1, lo=-5.0, hi=5.0,
+                       seed=2024, stream=100, generation=3)
+
+    ms = time_kernel_back_to_back(go, max(steps, 50), warmup, torch)
+    cells = pop * genes
+    gbs = 16.0 * cells / (ms * 1e-3) / 1e9
+    del P, F, C, W
+    return {"workload": "one EA generation: 16384 x 1024 genes, sphere fitness, tournament 2, "
+                        "rate 0.05, sigma 0.1, bounds [-5, 5]",
+            "kernel_ms": ms, "timing": "back-to-back launches between two events",
+            "genes_per_s": cells / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "kernel": "k_ea",
+                         "traffic": read_traffic("k_ea")}}
+
+
 def read_profile(kernel):
     """The committed rocprofv3 summary entry of a kernel (profiles/traffic.json),
     if it was taken on the current kernel source (else None)."""
@@ -406,10 +435,12 @@ def main():
         import tempfile
         cache = os.path.join(tempfile.gettempdir(), "zg_autotune_2p28.json")
         ctx.zg_autotune(cache, 8 * N_STREAMS * N_PER, use_cache=True)
-    if args.only in ("f32", "lcg", "mutate"):
+    if args.only in ("f32", "lcg", "mutate", "ea"):
         # one row alone (short runs under a profiler)
         if args.only == "f32":
             row = f32_row(ctx, Z, torch, args.steps, args.warmup)
+        elif args.only == "ea":
+            row = ea_row(ctx, Z, torch, args.steps, args.warmup)
         elif args.only == "lcg":
             row = c3_lcg(ctx, Z, torch, args.steps, args.warmup)
         else:
@@ -548,6 +579,7 @@ def main():
         line["c3_lcg"] = c3_lcg(ctx, Z, torch, args.steps, args.warmup)
         line["sequential"] = sequential_row(ctx, Z, torch, args.steps, args.warmup)
         line["c4_batch"] = c4_batch(ctx, Z, torch, 3)
+        line["ea_step"] = ea_row(ctx, Z, torch, args.steps, args.warmup)
     if args.serve_seconds > 0:
         from paper_2405_19493_amd import serve_bench
         note(f"serving, {args.serve_seconds:.0f} s per mode")

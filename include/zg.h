@@ -222,6 +222,37 @@ zg_status zg_uniform_words(zg_ctx *ctx, uint64_t *d_out, uint64_t n, zg_kind kin
 zg_status zg_mutate(zg_ctx *ctx, double *d_x, uint64_t n, double sigma, zg_kind kind,
                     uint64_t seed, uint32_t stream, uint64_t first_index, void *hip_stream);
 
+/* One generation of an evolutionary algorithm, fused (Section 1: the EA whose
+ * Gaussian mutation motivated the ziggurat; the paper does not describe the
+ * EA, so this is the read here).  A population of `pop` genomes of `genes`
+ * doubles (row-major) with their fitness (minimised) gives the next one:
+ *  - child c (key u = generation pop + c) copies the winner of a tournament
+ *    of `tournament` draws with replacement, draw t picking parent
+ *    floor(W(seed, stream, u, t) pop / 2^64) (SplitMix64 words); the first
+ *    draw of least fitness wins, a number beating a NaN;
+ *  - gene g (key w = u genes + g) mutates iff (W(seed, stream + 1, w, 0) >> 11)
+ *    < floor(rate 2^53), by x = x + sigma z (the product rounded first) with
+ *    z the FP64 ziggurat variate w of stream stream + 2; a mutated gene is
+ *    then clamped to [lo, hi] (a NaN stays NaN).
+ * d_children must not overlap d_parents.  d_winners (pop uint32, may be NULL)
+ * receives each child's parent.  All device pointers 8-byte aligned (4 for
+ * d_winners).  Asynchronous.  Errors: ZG_EINVAL (null, alignment, overlap,
+ * pop or genes 0, tournament outside 1..256, rate outside [0, 1], lo > hi,
+ * stream + 2 >= ZG_SM64_MAX_STREAMS), ZG_ERANGE ((generation + 1) pop genes
+ * past ZG_SM64_WINDOW), ZG_EHIP. */
+typedef struct zg_ea_params {
+  uint64_t seed;
+  uint64_t generation;
+  uint32_t stream;       /* streams stream, stream + 1, stream + 2 */
+  uint32_t tournament;   /* draws per tournament */
+  double rate;           /* per-gene mutation probability */
+  double sigma;
+  double lo, hi;         /* bounds of a mutated gene */
+} zg_ea_params;
+zg_status zg_ea_step(zg_ctx *ctx, const double *d_parents, const double *d_fitness,
+                     double *d_children, uint32_t *d_winners, uint32_t pop, uint32_t genes,
+                     const zg_ea_params *params, void *hip_stream);
+
 /* Sequential consumption (Section 2, Listing 2: nextGaussian(random) takes
  * its uniforms from one generator object, in call order): d_out[k] is the
  * k-th of n successive FP64 ziggurat variates that all read one generator in

@@ -91,6 +91,13 @@ class MzTableView(ctypes.Structure):
     ]
 
 
+class EaParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("generation", ctypes.c_uint64),
+                ("stream", ctypes.c_uint32), ("tournament", ctypes.c_uint32),
+                ("rate", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [
         ("out", ctypes.c_void_p),
@@ -161,6 +168,7 @@ def _load():
         "zg_fill_sequential_noalloc": [P, P, U64, ctypes.c_int, U64, U32, U64, P, P],
         "zg_sequential_workspace": [U64, P],
         "zg_mutate": [P, P, U64, D, ctypes.c_int, U64, U32, U64, P],
+        "zg_ea_step": [P, P, P, P, P, U32, U32, P, P],
         "zg_decide_words": [P, P, U64, P, P, P],
         "zg_error_flags": [P, P, ctypes.c_int],
         "zg_set_test_knob": [P, ctypes.c_int, ctypes.c_int64],
@@ -352,6 +360,31 @@ class Context:
         self._c(lib.zg_mutate(self.h, _ptr(x), x.numel(), float(sigma), kind, seed & (2**64 - 1),
                               stream, first_index, _stream(hip_stream)), "zg_mutate")
         return x
+
+    def zg_ea_step(self, parents, fitness, children, winners=None, tournament=2, rate=0.05,
+                   sigma=0.1, lo=-5.0, hi=5.0, seed=0, stream=0, generation=0,
+                   hip_stream=None):
+        """One EA generation (zg_ea_step): parents (pop x genes float64, C
+        order), fitness (pop float64) -> children (pop x genes), winners
+        (pop int32, optional)."""
+        if parents.dtype != torch.float64 or children.dtype != torch.float64 or \
+                fitness.dtype != torch.float64:
+            raise ValueError("the EA step works on float64")
+        if parents.dim() != 2 or parents.shape != children.shape or \
+                fitness.numel() != parents.shape[0]:
+            raise ValueError("parents and children: pop x genes; fitness: pop")
+        if not (parents.is_contiguous() and children.is_contiguous() and fitness.is_contiguous()):
+            raise ValueError("contiguous tensors only")
+        if winners is not None and (winners.dtype != torch.int32 or
+                                    winners.numel() != parents.shape[0]):
+            raise ValueError("winners: pop int32")
+        p = EaParams(seed & (2**64 - 1), generation, stream, tournament, float(rate),
+                     float(sigma), float(lo), float(hi))
+        pop, genes = parents.shape
+        self._c(lib.zg_ea_step(self.h, _ptr(parents), _ptr(fitness), _ptr(children),
+                               _ptr(winners) if winners is not None else None, pop, genes,
+                               ctypes.byref(p), _stream(hip_stream)), "zg_ea_step")
+        return children
 
     def zg_decide_words(self, words, cls, x, hip_stream=None):
         self._c(lib.zg_decide_words(self.h, _ptr(words), words.numel(), _ptr(cls), _ptr(x),

@@ -229,6 +229,44 @@ zg_status zg_fill(zg_ctx *ctx, void *d_out, uint64_t n, zg_dtype dtype, zg_metho
                          hip_stream);
 }
 
+zg_status zg_ea_step(zg_ctx *ctx, const double *d_parents, const double *d_fitness,
+                     double *d_children, uint32_t *d_winners, uint32_t pop, uint32_t genes,
+                     const zg_ea_params *p, void *hip_stream) {
+  if (!ctx || !p || !d_parents || !d_fitness || !d_children) return ZG_EINVAL;
+  if (pop == 0 || genes == 0) return ZG_EINVAL;
+  if (p->tournament < 1 || p->tournament > 256) return ZG_EINVAL;
+  if (!(p->rate >= 0.0 && p->rate <= 1.0) || !(p->lo <= p->hi)) return ZG_EINVAL;
+  if ((uint64_t)p->stream + 2 >= ZG_SM64_MAX_STREAMS) return ZG_EINVAL;
+  if ((uintptr_t)d_parents % 8 || (uintptr_t)d_fitness % 8 || (uintptr_t)d_children % 8 ||
+      (uintptr_t)d_winners % 4)
+    return ZG_EINVAL;
+  const uint64_t cells = (uint64_t)pop * genes;   // < 2^64: both below 2^32
+  const uintptr_t pa = (uintptr_t)d_parents, ca = (uintptr_t)d_children;
+  if (pa < ca + cells * 8 && ca < pa + cells * 8) return ZG_EINVAL;   // overlap
+  // the last gene key (generation + 1) pop genes - 1 stays inside the index window
+  if (p->generation >= ZG_SM64_WINDOW / cells || (p->generation + 1) * cells > ZG_SM64_WINDOW)
+    return ZG_ERANGE;
+  EaJob E{};
+  E.parents = d_parents;
+  E.fitness = d_fitness;
+  E.children = d_children;
+  E.winners = d_winners;
+  E.seed = p->seed;
+  E.generation = p->generation;
+  E.rate53 = (uint64_t)(p->rate * 9007199254740992.0);   // floor(rate 2^53), exact scaling
+  E.sigma = p->sigma;
+  E.lo = p->lo;
+  E.hi = p->hi;
+  E.pop = pop;
+  E.genes = genes;
+  E.tournament = p->tournament;
+  E.stream = p->stream;
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_ea(E, ctx->d_tables, ctx->dmax, ctx->d_flags, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "launch_ea");
+  return ZG_OK;
+}
+
 zg_status zg_mutate(zg_ctx *ctx, double *d_x, uint64_t n, double sigma, zg_kind kind,
                     uint64_t seed, uint32_t stream, uint64_t first_index, void *hip_stream) {
   if (!ctx) return ZG_EINVAL;

@@ -196,6 +196,18 @@ struct SeqJob {
 hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t *flags,
                        uint32_t tile, uint32_t waves, uint32_t head, uint32_t qcap,
                        uint32_t resident, uint32_t n_drain, uint32_t gsteps, hipStream_t stream);
+// One EA generation (zg_ea_step); rate53 = floor(rate 2^53).
+struct EaJob {
+  const double *parents;
+  const double *fitness;
+  double *children;
+  uint32_t *winners;
+  uint64_t seed, generation, rate53;
+  double sigma, lo, hi;
+  uint32_t pop, genes, tournament, stream;
+};
+hipError_t launch_ea(const EaJob &E, const DevTables *T, uint32_t dmax, uint32_t *flags,
+                     hipStream_t stream);
 hipError_t launch_words(uint64_t *out, uint64_t n, const DevTables *T, uint32_t kind,
                         uint64_t seed, uint32_t s, uint32_t d, uint64_t first, hipStream_t stream);
 hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, uint8_t *cls,

@@ -1449,6 +1449,83 @@ __global__ __launch_bounds__(1024) void k_zigws(Job J, const DevTables *__restri
   if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane == 0) raise_flag(flags, ZG_FLAG_BUDGET);
 }
 
+// ------------------------------------------------- one EA generation step
+//
+// One wave per child at a time (children: the global wave index, then every
+// wave count further).  The tournament's draws run in lanes 0..63, one
+// fitness load each; the winner is taken from the lanes' values in draw
+// order (the first draw of least fitness, a number beating a NaN).  The
+// child's genes then go 64 at a time, one per lane: the winner's gene, the
+// mutation decision from the gene's own word, the ziggurat variate (resolve:
+// the fast path and, rarely, the slow path) in the lanes that mutate only,
+// the clamp, a coalesced store.
+
+DEV double readlane_f64(double x, uint32_t q) {
+  const long long b = __double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, (int)q);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), (int)q);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int KIND>
+__global__ __launch_bounds__(1024) void k_ea(EaJob E, const DevTables *__restrict__ T,
+                                             uint32_t dmax, uint32_t *flags) {
+  __shared__ LdsTabs L;
+  load_tabs<OP_ZIG64>(T, L);
+  __syncthreads();
+  const double r = T->r;
+  const uint32_t lane = lane_id();
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const uint64_t tw = (uint64_t)gridDim.x * nw;
+  Job Jz{};   // the variates' key: the seed (stream and index per gene)
+  Jz.seed = E.seed;
+  Jz.kind = KIND;
+  Jz.op = OP_ZIG64;
+  bool budget = false;
+  for (uint64_t c = (uint64_t)blockIdx.x * nw + wave; c < E.pop; c += tw) {
+    const uint64_t u = E.generation * E.pop + c;
+    uint32_t best = 0;
+    double fbest = 0.0;
+    for (uint32_t t0 = 0; t0 < E.tournament; t0 += 64) {
+      const uint32_t t = t0 + lane;
+      uint32_t idx = 0;
+      double f = 0.0;
+      if (t < E.tournament) {
+        idx = (uint32_t)__umul64hi(sm64_word(E.seed, E.stream, u, t), (uint64_t)E.pop);
+        f = E.fitness[idx];
+      }
+      const uint32_t m = E.tournament - t0 < 64 ? E.tournament - t0 : 64;
+      for (uint32_t q = 0; q < m; ++q) {
+        const uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)idx, (int)q);
+        const double fq = readlane_f64(f, q);
+        if ((t0 == 0 && q == 0) || fq < fbest || (isnan(fbest) && !isnan(fq))) {
+          best = iq;
+          fbest = fq;
+        }
+      }
+    }
+    if (lane == 0 && E.winners) E.winners[c] = best;
+    const double *prow = E.parents + (uint64_t)best * E.genes;
+    double *crow = E.children + c * E.genes;
+    const uint64_t w0 = u * E.genes;
+    for (uint32_t g0 = 0; g0 < E.genes; g0 += 64) {
+      const uint32_t g = g0 + lane;
+      if (g < E.genes) {
+        double x = prow[g];
+        const uint64_t w = w0 + g;
+        if ((sm64_word(E.seed, E.stream + 1, w, 0) >> 11) < E.rate53) {
+          const double z = resolve<OP_ZIG64, KIND>(Jz, L, T, r, dmax, E.stream + 2, w, budget);
+          x = x + E.sigma * z;
+          x = x < E.lo ? E.lo : (x > E.hi ? E.hi : x);
+        }
+        crow[g] = x;
+      }
+    }
+  }
+  if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane == 0) raise_flag(flags, ZG_FLAG_BUDGET);
+}
+
 // ---------------------------------------------------------------- kernels
 
 // Polar method: one tile per wave; tile t covers [head + t tile, + tile).
@@ -2088,6 +2165,20 @@ hipError_t launch_fill(const Job &J, const DevTables *T, uint32_t dmax, uint32_t
       return launch_kind<OP_MUTATE>(J, T, dmax, flags, tile, waves, head, qcap, resident, n_drain,
                                     gsteps, stream);
   }
+}
+
+hipError_t launch_ea(const EaJob &E, const DevTables *T, uint32_t dmax, uint32_t *flags,
+                     hipStream_t stream) {
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  // 16-wave workgroups, one child per wave at a time, at most 2 per CU
+  const uint64_t want = ((uint64_t)E.pop + 15) / 16;
+  const uint64_t cap = 2ull * (uint64_t)cus;
+  const uint32_t blocks = (uint32_t)(want < cap ? want : cap);
+  hipLaunchKernelGGL((k_ea<ZG_SPLITMIX64>), dim3(blocks), dim3(1024), 0, stream, E, T, dmax,
+                     flags);
+  return hipGetLastError();
 }
 
 hipError_t launch_words(uint64_t *out, uint64_t n, const DevTables *T, uint32_t kind,

@@ -198,7 +198,56 @@ static int fill_only(char **a) {
   return 0;
 }
 
+// ea POP GENES K SEED STREAM GEN RATE SIGMA LO HI PARENTS FITNESS CHILDREN WINNERS:
+// one EA generation (launch_ea) from float64 files, outputs to files.
+static int ea_only(char **a) {
+  EaJob E{};
+  E.pop = (uint32_t)atoi(a[0]);
+  E.genes = (uint32_t)atoi(a[1]);
+  E.tournament = (uint32_t)atoi(a[2]);
+  E.seed = strtoull(a[3], 0, 10);
+  E.stream = (uint32_t)atoi(a[4]);
+  E.generation = strtoull(a[5], 0, 10);
+  E.rate53 = (uint64_t)(atof(a[6]) * 9007199254740992.0);
+  E.sigma = atof(a[7]);
+  E.lo = atof(a[8]);
+  E.hi = atof(a[9]);
+  const uint64_t cells = (uint64_t)E.pop * E.genes;
+  double *P = (double *)malloc(cells * 8), *F = (double *)malloc((size_t)E.pop * 8);
+  double *C = (double *)malloc(cells * 8);
+  uint32_t *W = (uint32_t *)malloc((size_t)E.pop * 4);
+  FILE *f = fopen(a[10], "rb");
+  if (!f || fread(P, 8, cells, f) != cells) return 3;
+  fclose(f);
+  f = fopen(a[11], "rb");
+  if (!f || fread(F, 8, E.pop, f) != E.pop) return 3;
+  fclose(f);
+  E.parents = P;
+  E.fitness = F;
+  E.children = C;
+  E.winners = W;
+  DevTables *T = host_tables();
+  uint32_t *flags = (uint32_t *)calloc(1, sizeof(uint32_t));
+  if (launch_ea(E, T, ZG_MAX_DRAWS, flags, nullptr) != hipSuccess) return 4;
+  f = fopen(a[12], "wb");
+  fwrite(C, 8, cells, f);
+  fclose(f);
+  f = fopen(a[13], "wb");
+  fwrite(W, 4, E.pop, f);
+  fclose(f);
+  std::fprintf(stderr, "flags=%u\n", *flags);
+  free(P);
+  free(F);
+  free(C);
+  free(W);
+  free(flags);
+  delete T;
+  pools.clear();
+  return 0;
+}
+
 int main(int argc, char **argv) {
+  if (argc >= 16 && std::strcmp(argv[1], "ea") == 0) return ea_only(argv + 2);
   if (argc == 4 && std::strcmp(argv[1], "scan") == 0)
     return scan_only((uint32_t)strtoul(argv[2], 0, 10), strtoull(argv[3], 0, 10));
   if (argc >= 13 && std::strcmp(argv[1], "fill") == 0) return fill_only(argv + 2);

@@ -95,6 +95,9 @@ hipError_t launch_fill(const Job &, const DevTables *, uint32_t, uint32_t *, uin
                        uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, hipStream_t) {
   return hipErrorInvalidValue;
 }
+hipError_t launch_ea(const EaJob &, const DevTables *, uint32_t, uint32_t *, hipStream_t) {
+  return hipErrorInvalidValue;
+}
 hipError_t launch_words(uint64_t *, uint64_t, const DevTables *, uint32_t, uint64_t, uint32_t,
                         uint32_t, uint64_t, hipStream_t) {
   return hipErrorInvalidValue;

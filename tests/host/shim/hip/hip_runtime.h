@@ -58,6 +58,7 @@ struct EmuWave {
   std::unique_ptr<std::barrier<>> bar;
   std::atomic<uint64_t> acc{0};
   uint64_t val = 0;
+  uint32_t lanes[64] = {};
 };
 extern std::vector<std::unique_ptr<EmuWave>> emu_waves;
 extern std::unique_ptr<std::barrier<>> emu_block_bar;
@@ -84,6 +85,19 @@ inline uint32_t emu_rfl(uint32_t x) {
   w.bar->arrive_and_wait();
   return r;
 }
+inline int emu_readlane(int x, int q) {
+  EmuWave &w = *emu_waves[threadIdx.x >> 6];
+  w.lanes[threadIdx.x & 63u] = (uint32_t)x;
+  w.bar->arrive_and_wait();
+  const int r = (int)w.lanes[q & 63];
+  w.bar->arrive_and_wait();
+  return r;
+}
+inline uint64_t __umul64hi(uint64_t a, uint64_t b) {
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+}
+#define __builtin_amdgcn_readlane(x, q) emu_readlane(x, q)
+using std::isnan;
 #define __builtin_amdgcn_ballot_w64(p) emu_ballot(p)
 #define __builtin_amdgcn_readfirstlane(x) emu_rfl(x)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
