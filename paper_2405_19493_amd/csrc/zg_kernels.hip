@@ -1452,13 +1452,24 @@ __global__ __launch_bounds__(1024) void k_zigws(Job J, const DevTables *__restri
 // ------------------------------------------------- one EA generation step
 //
 // One wave per child at a time (children: the global wave index, then every
-// wave count further).  The tournament's draws run in lanes 0..63, one
-// fitness load each; the winner is taken from the lanes' values in draw
-// order (the first draw of least fitness, a number beating a NaN).  The
-// child's genes then go 64 at a time, one per lane: the winner's gene, the
-// mutation decision from the gene's own word, the ziggurat variate (resolve:
-// the fast path and, rarely, the slow path) in the lanes that mutate only,
-// the clamp, a coalesced store.
+// wave count further).  The tournament's draws run in lanes 0..63; the
+// winner is taken in draw order (the first draw of least fitness, a number
+// beating a NaN), the fitness of each draw read by a scalar load (per-lane
+// loads, for tournaments of more than 64 draws).  The child's genes then go
+// in groups of EA_U chunks of 64, one gene per lane per chunk:
+// - the winner's 64 EA_U genes loaded, all loads issued before any is used
+//   (EA_U x 512 bytes in flight per wave);
+// - each gene's mutation decided from its own word, whose key is a
+//   wave-uniform part plus a per-lane constant (an add per gene, not a
+//   multiply); the mutating genes listed in LDS;
+// - the list's variates drawn 64 at a time, one gene per lane (ziggurat fast
+//   path and, rarely, the slow path), back into LDS: the variate's code runs
+//   once per 64 mutating genes, not once per chunk for its few mutating
+//   lanes (5% of the genes at the usual rates);
+// - each chunk stored once: the winner's gene, or it plus sigma times its
+//   variate, clamped.  Whole cache lines are written at once; a line
+//   written in two parts (the unmutated genes, later the mutated ones) can
+//   leave L2 in between and cost HBM a second, partial write.
 
 DEV double readlane_f64(double x, uint32_t q) {
   const long long b = __double_as_longlong(x);
@@ -1467,60 +1478,163 @@ DEV double readlane_f64(double x, uint32_t q) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-template <int KIND>
-__global__ __launch_bounds__(1024) void k_ea(EaJob E, const DevTables *__restrict__ T,
-                                             uint32_t dmax, uint32_t *flags) {
-  __shared__ LdsTabs L;
-  load_tabs<OP_ZIG64>(T, L);
+constexpr uint32_t EA_WAVES = 8;    // waves per workgroup
+constexpr uint32_t EA_BPC = 4;      // workgroups per compute unit in the grid
+
+// U: gene chunks of 64 per group (2, 4 or 8, from the genome's length)
+template <uint32_t U>
+struct EaLds {
+  LdsTabs t;
+  double z[EA_WAVES][64 * U];     // their variates
+  uint32_t g[EA_WAVES][64 * U];   // the group's mutating genes
+};
+
+// The draws of one tournament chunk (draws t0 + lane): winner index, fitness.
+DEV void ea_draws(const EaJob &E, uint64_t u, uint32_t t0, uint32_t &idx, double &f) {
+  const uint32_t t = t0 + lane_id();
+  idx = 0;
+  f = 0.0;
+  if (t < E.tournament) {
+    idx = (uint32_t)__umul64hi(sm64_word(E.seed, E.stream, u, t), (uint64_t)E.pop);
+    f = E.fitness[idx];
+  }
+}
+
+// A fitness value read with a wave-uniform index, through the constant
+// address space: a scalar load, waited for on its own counter, so that the
+// fold does not wait for the wave's outstanding gene stores.
+DEV double fitness_uniform(const double *f, uint32_t i) {
+  return ((const __attribute__((address_space(4))) double *)f)[i];
+}
+
+// Folds tournament draws 0 .. k - 1 of child key u (k <= 64): the winners'
+// indices from the lanes, their fitness by scalar loads.
+DEV void ea_fold_short(const EaJob &E, uint64_t u, uint32_t &best) {
+  const uint32_t t = lane_id();
+  const uint32_t idx =
+      t < E.tournament
+          ? (uint32_t)__umul64hi(sm64_word(E.seed, E.stream, u, t), (uint64_t)E.pop)
+          : 0u;
+  double fbest = 0.0;
+  for (uint32_t q = 0; q < E.tournament; ++q) {
+    const uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)idx, (int)q);
+    const double fq = fitness_uniform(E.fitness, iq);
+    if (q == 0 || fq < fbest || (isnan(fbest) && !isnan(fq))) {
+      best = iq;
+      fbest = fq;
+    }
+  }
+}
+
+// Folds the draws t0 .. t0 + m - 1 (lanes 0 .. m - 1) into (best, fbest).
+DEV void ea_fold(uint32_t idx, double f, uint32_t m, bool first, uint32_t &best, double &fbest) {
+  for (uint32_t q = 0; q < m; ++q) {
+    const uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)idx, (int)q);
+    const double fq = readlane_f64(f, q);
+    if ((first && q == 0) || fq < fbest || (isnan(fbest) && !isnan(fq))) {
+      best = iq;
+      fbest = fq;
+    }
+  }
+}
+
+template <int KIND, uint32_t EA_U>
+__global__ __launch_bounds__(64 * EA_WAVES) void k_ea(EaJob E, const DevTables *__restrict__ T,
+                                                     uint32_t dmax, uint32_t *flags) {
+  __shared__ EaLds<EA_U> L;
+  load_tabs<OP_ZIG64>(T, L.t);
   __syncthreads();
   const double r = T->r;
   const uint32_t lane = lane_id();
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wave = uni(threadIdx.x >> 6);
+  uint32_t *ql = L.g[wave];
+  double *qz = L.z[wave];
   const uint64_t tw = (uint64_t)gridDim.x * nw;
   Job Jz{};   // the variates' key: the seed (stream and index per gene)
   Jz.seed = E.seed;
   Jz.kind = KIND;
   Jz.op = OP_ZIG64;
   bool budget = false;
+  // the mutation word of gene w is mix64(seed + GAMMA (1 + (stream + 1) 2^48 + w)):
+  // a wave-uniform part per chunk plus GAMMA lane (mod 2^64).  The per-lane
+  // term is opaque to the compiler, which would otherwise fold the sum back
+  // into a multiply per gene.
+  uint64_t klane = GAMMA * (uint64_t)lane;
+  asm volatile("" : "+v"(klane));
+
   for (uint64_t c = (uint64_t)blockIdx.x * nw + wave; c < E.pop; c += tw) {
     const uint64_t u = E.generation * E.pop + c;
     uint32_t best = 0;
-    double fbest = 0.0;
-    for (uint32_t t0 = 0; t0 < E.tournament; t0 += 64) {
-      const uint32_t t = t0 + lane;
-      uint32_t idx = 0;
-      double f = 0.0;
-      if (t < E.tournament) {
-        idx = (uint32_t)__umul64hi(sm64_word(E.seed, E.stream, u, t), (uint64_t)E.pop);
-        f = E.fitness[idx];
-      }
-      const uint32_t m = E.tournament - t0 < 64 ? E.tournament - t0 : 64;
-      for (uint32_t q = 0; q < m; ++q) {
-        const uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)idx, (int)q);
-        const double fq = readlane_f64(f, q);
-        if ((t0 == 0 && q == 0) || fq < fbest || (isnan(fbest) && !isnan(fq))) {
-          best = iq;
-          fbest = fq;
-        }
+    if (E.tournament <= 64) {
+      ea_fold_short(E, u, best);
+    } else {
+      double fbest = 0.0;
+      for (uint32_t t0 = 0; t0 < E.tournament; t0 += 64) {
+        uint32_t idx;
+        double f;
+        ea_draws(E, u, t0, idx, f);
+        const uint32_t m = E.tournament - t0 < 64 ? E.tournament - t0 : 64;
+        ea_fold(idx, f, m, t0 == 0, best, fbest);
       }
     }
     if (lane == 0 && E.winners) E.winners[c] = best;
     const double *prow = E.parents + (uint64_t)best * E.genes;
     double *crow = E.children + c * E.genes;
     const uint64_t w0 = u * E.genes;
-    for (uint32_t g0 = 0; g0 < E.genes; g0 += 64) {
-      const uint32_t g = g0 + lane;
-      if (g < E.genes) {
-        double x = prow[g];
-        const uint64_t w = w0 + g;
-        if ((sm64_word(E.seed, E.stream + 1, w, 0) >> 11) < E.rate53) {
-          const double z = resolve<OP_ZIG64, KIND>(Jz, L, T, r, dmax, E.stream + 2, w, budget);
-          x = x + E.sigma * z;
+    // key of gene g0 of this chunk group in lane 0; advanced per group
+    uint64_t kg = E.seed + GAMMA * (1ull + ((uint64_t)(E.stream + 1) << 48) + w0);
+    for (uint32_t g0 = 0; g0 < E.genes; g0 += 64 * EA_U, kg += GAMMA * (64ull * EA_U)) {
+      // unconditional loads (a lane past the row's end reads its last gene)
+      double xv[EA_U];
+#pragma unroll
+      for (uint32_t k = 0; k < EA_U; ++k) {
+        const uint32_t g = g0 + 64 * k + lane;
+        xv[k] = prow[g < E.genes ? g : E.genes - 1];
+      }
+      // the decisions; the mutating genes listed, chunk by chunk
+      uint32_t qn = 0;          // list length (wave-uniform)
+      uint32_t at[EA_U];        // a mutating lane's list position
+      uint32_t mutk = 0;        // bit k: this lane's gene of chunk k mutates
+#pragma unroll
+      for (uint32_t k = 0; k < EA_U; ++k) {
+        const uint32_t g = g0 + 64 * k + lane;
+        const uint64_t key = kg + GAMMA * (64ull * k) + klane;
+        const bool mut = g < E.genes && (mix64(key) >> 11) < E.rate53;
+        const uint64_t bm = __builtin_amdgcn_ballot_w64(mut);
+        at[k] = qn + prefix_below(bm);
+        if (mut) {
+          ql[at[k]] = g;
+          mutk |= 1u << k;
+        }
+        qn = uni(qn + (uint32_t)__popcll(bm));
+      }
+      __builtin_amdgcn_wave_barrier();
+      // the variates, 64 genes at a time, one per lane
+      for (uint32_t b = 0; b < qn; b += 64) {
+        if (b + lane < qn) {
+          const uint32_t g = ql[b + lane];
+          qz[b + lane] =
+              resolve<OP_ZIG64, KIND>(Jz, L.t, T, r, dmax, E.stream + 2, w0 + g, budget);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      // each chunk stored once, whole lines: the winner's gene, or it plus
+      // sigma times its variate, clamped
+#pragma unroll
+      for (uint32_t k = 0; k < EA_U; ++k) {
+        const uint32_t g = g0 + 64 * k + lane;
+        // the value is needed here, on every path: the wait for its load is
+        // then the exact count, not a full drain at the next group's loads
+        asm volatile("" ::"v"(xv[k]));
+        double x = xv[k];
+        if (mutk & (1u << k)) {
+          x = x + E.sigma * qz[at[k]];
           x = x < E.lo ? E.lo : (x > E.hi ? E.hi : x);
         }
-        crow[g] = x;
+        if (g < E.genes) crow[g] = x;
       }
+      __builtin_amdgcn_wave_barrier();
     }
   }
   if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane == 0) raise_flag(flags, ZG_FLAG_BUDGET);
@@ -2172,12 +2286,20 @@ hipError_t launch_ea(const EaJob &E, const DevTables *T, uint32_t dmax, uint32_t
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  // 16-wave workgroups, one child per wave at a time, at most 2 per CU
-  const uint64_t want = ((uint64_t)E.pop + 15) / 16;
-  const uint64_t cap = 2ull * (uint64_t)cus;
+  // EA_WAVES-wave workgroups, one child per wave at a time, at most EA_BPC
+  // per CU; groups of 512 genes, or of 256 or 128 for short genomes
+  const uint64_t want = ((uint64_t)E.pop + EA_WAVES - 1) / EA_WAVES;
+  const uint64_t cap = (uint64_t)EA_BPC * (uint64_t)cus;
   const uint32_t blocks = (uint32_t)(want < cap ? want : cap);
-  hipLaunchKernelGGL((k_ea<ZG_SPLITMIX64>), dim3(blocks), dim3(1024), 0, stream, E, T, dmax,
-                     flags);
+  if (E.genes > 256)
+    hipLaunchKernelGGL((k_ea<ZG_SPLITMIX64, 8>), dim3(blocks), dim3(64 * EA_WAVES), 0, stream, E,
+                       T, dmax, flags);
+  else if (E.genes > 128)
+    hipLaunchKernelGGL((k_ea<ZG_SPLITMIX64, 4>), dim3(blocks), dim3(64 * EA_WAVES), 0, stream, E,
+                       T, dmax, flags);
+  else
+    hipLaunchKernelGGL((k_ea<ZG_SPLITMIX64, 2>), dim3(blocks), dim3(64 * EA_WAVES), 0, stream, E,
+                       T, dmax, flags);
   return hipGetLastError();
 }
 

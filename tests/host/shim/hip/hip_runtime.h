@@ -100,7 +100,10 @@ inline uint64_t __umul64hi(uint64_t a, uint64_t b) {
 using std::isnan;
 #define __builtin_amdgcn_ballot_w64(p) emu_ballot(p)
 #define __builtin_amdgcn_readfirstlane(x) emu_rfl(x)
-#define __builtin_amdgcn_wave_barrier() ((void)0)
+// a wave's lanes in step at this point: LDS writes made before it by any lane
+// are seen after it by every lane, as they are in a wave on the GPU
+inline void emu_wave_barrier() { emu_waves[threadIdx.x >> 6]->bar->arrive_and_wait(); }
+#define __builtin_amdgcn_wave_barrier() emu_wave_barrier()
 inline uint32_t emu_mbcnt_lo(uint32_t m, uint32_t a) { uint32_t l = threadIdx.x & 63u; return a + __builtin_popcount(l >= 32 ? m : (m & ((1u << l) - 1u))); }
 inline uint32_t emu_mbcnt_hi(uint32_t m, uint32_t a) { uint32_t l = threadIdx.x & 63u; return a + (l < 32 ? 0 : __builtin_popcount(m & ((l == 32 ? 0u : (1u << (l - 32)) - 1u)))); }
 #define __builtin_amdgcn_mbcnt_lo(m, a) emu_mbcnt_lo(m, a)

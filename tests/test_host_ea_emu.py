@@ -2,7 +2,9 @@
 stand-in and AddressSanitizer (tests/host/kernel_emu.cpp, mode ea), run
 through launch_ea: winners and children equal the oracle's bit for bit, with
 tournaments of 1 to 70 draws (more draws than lanes), NaN and tied fitness,
-one-gene genomes and ragged gene counts; no access leaves its buffer."""
+one-gene genomes and ragged gene counts, and rates up to 1 (several rounds of
+64 mutating genes per chunk group, and leftovers carried between groups);
+no access leaves its buffer."""
 import os
 
 import numpy as np
@@ -22,10 +24,12 @@ def emu(tmp_path_factory):
 
 
 CASES = [(37, 70, 2, 3, 0.1, 0.5, -2.0, 2.0, False), (5, 1, 1, 0, 1.0, 3.0, -1.0, 1.0, False),
-         (300, 129, 4, 7, 0.05, 0.1, -5.0, 5.0, True), (64, 64, 70, 1, 0.5, 1.0, -1.5, 1.5, True)]
+         (300, 129, 4, 7, 0.05, 0.1, -5.0, 5.0, True), (64, 64, 70, 1, 0.5, 1.0, -1.5, 1.5, True),
+         (20, 700, 3, 2, 0.9, 0.2, -3.0, 3.0, False), (9, 769, 2, 5, 1.0, 0.5, -4.0, 4.0, False)]
 
 
-@pytest.mark.parametrize("case", CASES, ids=["ragged", "one-gene", "nan", "wide-tournament"])
+@pytest.mark.parametrize("case", CASES, ids=["ragged", "one-gene", "nan", "wide-tournament",
+                                              "most-mutate", "all-mutate"])
 def test_ea_kernel_equals_oracle(emu, orc, case):
     pop, genes, k, gen, rate, sigma, lo, hi, nanfit = case
     d, exe = emu
