@@ -25,7 +25,7 @@ const zg_tune DEFAULT_TUNE[ZG_TUNE_CLASSES] = {
     {4096, 16, 2, 0, 3, 4},   // FILL_F32: wave-specialised, 3 drain waves
     {2048, 8, 0, 0, 0, 4},    // POLAR
     {2048, 16, 2, 0, 4, 4},   // MUTATE: wave-specialised, 4 drain waves
-    {2048, 8, 4, 0, 0, 4},    // BATCH (k_batch is bounded to 512 threads)
+    {2048, 8, 4, 0, 2, 4},    // BATCH: wave-specialised class kernels, 2 drain waves of 8
     {2048, 16, 2, 0, 0, 4},   // FILL_MZ: block-pooled, persistent, 2048 x 16 tiles
 };
 

@@ -24,6 +24,18 @@ void destroy_graph(hipGraph_t &g, hipGraphExec_t &x) {
 }
 }  // namespace
 
+// The ziggurat classes run wave-specialised when the shape has drain waves
+// and at least one streaming wave.
+static bool batch_ws(const zg_tune &bt) {
+  return bt.drain_waves > 0 && bt.drain_waves < bt.waves_per_block;
+}
+
+static bool same_tune(const zg_tune &a, const zg_tune &b) {
+  return a.tile == b.tile && a.waves_per_block == b.waves_per_block &&
+         a.batch_blocks_per_cu == b.batch_blocks_per_cu && a.queue_cap == b.queue_cap &&
+         a.drain_waves == b.drain_waves && a.group_steps == b.group_steps;
+}
+
 zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
                      uint32_t *const *done_flags, uint32_t done_value, BatchPlan *plan,
                      uint64_t *const *first_host) {
@@ -32,6 +44,7 @@ zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
   plan->items.clear();
   plan->total_elems = 0;
   const zg_tune bt = ctx->tune[ZG_TUNE_BATCH];
+  plan->bt = bt;
   std::unordered_map<int32_t, size_t> last_of;   // handle -> planned index of its last request
   std::unordered_map<int32_t, uint64_t> off_of;  // handle -> running offset
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -213,9 +226,11 @@ zg_status BatchSlot::ensure(zg_ctx *ctx, size_t nreq, size_t nitems) {
   return ZG_OK;
 }
 
-zg_status BatchSlot::build_graphs(zg_ctx *ctx) {
-  if (x_full) return ZG_OK;
-  const zg_tune bt = ctx->tune[ZG_TUNE_BATCH];
+zg_status BatchSlot::build_graphs(zg_ctx *ctx, const zg_tune &bt) {
+  if (x_full && same_tune(graph_bt, bt)) return ZG_OK;
+  invalidate_graphs();
+  graph_bt = bt;
+  const bool ws = batch_ws(bt);
   BatchHeader *dH = (BatchHeader *)d_buf;
   DevRequest *dR = d_reqs();
   DevTables *T = ctx->d_tables;
@@ -236,7 +251,7 @@ zg_status BatchSlot::build_graphs(zg_ctx *ctx) {
   hipKernelNodeParams kc[BATCH_CLASSES];
   for (int c = 0; c < BATCH_CLASSES; ++c) {
     kc[c] = hipKernelNodeParams{};
-    kc[c].func = (void *)kernel_batch_class(c);
+    kc[c].func = (void *)kernel_batch_class(c, ws);
     kc[c].gridDim = dim3((uint32_t)(ctx->num_cus * bt.batch_blocks_per_cu));
     kc[c].blockDim = dim3(64 * bt.waves_per_block);
     kc[c].sharedMemBytes = (unsigned)batch_class_lds_bytes(c, bt.waves_per_block);
@@ -289,7 +304,10 @@ zg_status BatchSlot::launch(zg_ctx *ctx, const BatchPlan &plan, hipStream_t stre
                             hipStream_t run_stream, hipEvent_t prep_done) {
   zg_status st = ensure(ctx, plan.reqs.size(), plan.items.size());
   if (st != ZG_OK) return st;
-  st = build_graphs(ctx);
+  // the kernels, the header and the plan's tiles all follow the plan's shape
+  const zg_tune &bt = plan.bt;
+  const bool ws = batch_ws(bt);
+  st = build_graphs(ctx, bt);
   if (st != ZG_OK) return st;
   BatchHeader *H = (BatchHeader *)h_buf;
   std::memset(H, 0, sizeof(*H));
@@ -297,9 +315,17 @@ zg_status BatchSlot::launch(zg_ctx *ctx, const BatchPlan &plan, hipStream_t stre
   H->dmax = ctx->dmax;
   H->n_items = (uint32_t)plan.items.size();
   H->items_off = (uint32_t)(sizeof(BatchHeader) + plan.reqs.size() * sizeof(DevRequest));
+  H->ws_drain = ws ? bt.drain_waves : 0;
+  H->ws_gsteps = bt.group_steps;
   for (int c = 0; c < BATCH_CLASSES; ++c) {
     H->cls_off[c] = plan.cls_off[c];
     H->cls_cnt[c] = plan.cls_cnt[c];
+    // a class's request tiles hold tile x waves elements (twice the tile for
+    // FP32, as plan_batch cuts them), in groups of group_steps steps
+    const uint32_t wave_tile = c / 2 == 1 ? 2 * bt.tile : bt.tile;
+    const uint64_t per = (uint64_t)((wave_tile + 255) / 256 * 256) * bt.waves_per_block;
+    const uint64_t ge = 256ull * bt.group_steps;
+    H->cls_groups[c] = (uint32_t)((per + ge - 1) / ge);
   }
   std::memcpy((char *)h_buf + sizeof(BatchHeader), plan.reqs.data(),
               plan.reqs.size() * sizeof(DevRequest));
@@ -311,7 +337,6 @@ zg_status BatchSlot::launch(zg_ctx *ctx, const BatchPlan &plan, hipStream_t stre
   if (full && plan.reqs.size() <= DIRECT_MAX) {
     // a few requests: plain launches of the classes with work, each grid
     // sized to its tiles (cheaper than updating and launching the graph)
-    const zg_tune bt = ctx->tune[ZG_TUNE_BATCH];
     const uint32_t cap_blocks = (uint32_t)(ctx->num_cus * bt.batch_blocks_per_cu);
     BatchHeader *dH = (BatchHeader *)d_buf;
     DevRequest *dR = d_reqs();
@@ -319,7 +344,6 @@ zg_status BatchSlot::launch(zg_ctx *ctx, const BatchPlan &plan, hipStream_t stre
     uint32_t *flags = ctx->d_flags;
     uint64_t *counters = ctx->d_counters;
     void *reserve_args[] = {&dR, &dH, &counters, &flags};
-    void *class_args[] = {&dR, &dH, &T, &flags};
     void *complete_args[] = {&dR, &dH};
     e = hipMemcpyAsync(d_buf, h_buf, bytes, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
@@ -327,8 +351,7 @@ zg_status BatchSlot::launch(zg_ctx *ctx, const BatchPlan &plan, hipStream_t stre
     for (int c = 0; c < BATCH_CLASSES && e == hipSuccess; ++c) {
       if (!plan.cls_cnt[c]) continue;
       const uint32_t grid = plan.cls_cnt[c] < cap_blocks ? plan.cls_cnt[c] : cap_blocks;
-      e = hipLaunchKernel(kernel_batch_class(c), dim3(grid), dim3(64 * bt.waves_per_block),
-                          class_args, batch_class_lds_bytes(c, bt.waves_per_block), stream);
+      e = launch_batch_class(c, ws, grid, bt.waves_per_block, dR, dH, T, flags, stream);
     }
     if (e == hipSuccess)
       e = hipLaunchKernel(kernel_complete(), dim3(1), dim3(256), complete_args, 0, stream);

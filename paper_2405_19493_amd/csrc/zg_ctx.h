@@ -36,6 +36,7 @@ struct BatchPlan {
   uint32_t cls_off[BATCH_CLASSES] = {};
   uint32_t cls_cnt[BATCH_CLASSES] = {};
   uint64_t total_elems = 0;
+  zg_tune bt{};   // the batch launch shape the plan was made for
 };
 
 struct BatchSlot {
@@ -48,13 +49,14 @@ struct BatchSlot {
   hipGraphNode_t cpy_full = nullptr, cpy_prep = nullptr;
   hipGraphNode_t cls_full[BATCH_CLASSES] = {}, cls_run[BATCH_CLASSES] = {};
   uint32_t mask_full = 0xFFu, mask_run = 0xFFu;   // class nodes currently enabled
+  zg_tune graph_bt{};   // the launch shape the graphs were built for
   hipEvent_t done = nullptr;   // recorded after the last use of the staging buffer
   bool busy = false;
   bool recorded = false;
 
   DevRequest *d_reqs() const { return (DevRequest *)((char *)d_buf + sizeof(BatchHeader)); }
   zg_status ensure(struct ::zg_ctx *ctx, size_t nreq, size_t nitems);
-  zg_status build_graphs(struct ::zg_ctx *ctx);
+  zg_status build_graphs(struct ::zg_ctx *ctx, const zg_tune &bt);
   void invalidate_graphs();
   void release();
   // Uploads the plan and launches.  full: one graph {copy, reserve, batch} on

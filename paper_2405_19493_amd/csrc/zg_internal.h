@@ -140,7 +140,12 @@ struct BatchHeader {
   uint32_t items_off;   // byte offset of the items from the header
   uint32_t cls_off[BATCH_CLASSES];
   uint32_t cls_cnt[BATCH_CLASSES];
-  uint64_t pad[6];
+  // wave-specialised class kernels (ws_drain > 0): drain waves per
+  // workgroup, steps per streaming group, and groups per item of each class
+  uint32_t ws_drain;
+  uint32_t ws_gsteps;
+  uint32_t cls_groups[BATCH_CLASSES];
+  uint64_t pad[1];
 };
 
 // Sequential consumption (one generator read in order): the parallel pass
@@ -242,7 +247,12 @@ hipError_t seq_scratch_ptr(int dev, void **out);
 const void *kernel_reserve();
 const void *kernel_complete();
 // The kernel of a work class, and its dynamic LDS for `waves` waves.
-const void *kernel_batch_class(int cls);
+// Class kernel of a batch: the wave-specialised one (ziggurat classes) when
+// ws, else the block-pooled one.
+const void *kernel_batch_class(int cls, bool ws);
+hipError_t launch_batch_class(int cls, bool ws, uint32_t grid, uint32_t waves, DevRequest *R,
+                              const BatchHeader *H, const DevTables *T, uint32_t *flags,
+                              hipStream_t stream);
 size_t batch_class_lds_bytes(int cls, uint32_t waves);
 
 zg_status build_table(zg_table_view *t);

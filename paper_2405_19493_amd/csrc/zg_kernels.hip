@@ -1236,6 +1236,86 @@ DEV uint32_t lds_load(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Ring and retry entries of the batch kernel carry the request: ring entry
+// (request << 40 | element) + 1, retry entry element | draw << 40 |
+// request << 49 (elements < 2^40, draws <= ZG_MAX_DRAWS < 2^9, requests <
+// ZG_MAX_BATCH = 2^15).  The plain kernel's entries are element + 1, and
+// element | draw << ENT_D.
+constexpr uint32_t WSB_E = 40;
+constexpr uint64_t WSB_EMASK = (1ull << WSB_E) - 1;
+constexpr uint32_t WSB_R = 49;
+static_assert(ZG_MAX_BATCH <= (1u << (64 - WSB_R)) && ZG_MAX_DRAWS < (1u << (WSB_R - WSB_E)),
+              "batch ring entry fields");
+
+// Streams elements [gs, ge) of a job (one group: whole steps, and a ragged
+// last one at a job's end) with 128-bit stores and placeholders, then
+// publishes the lane's slow elements in the ring, each as tag | element.
+template <int OP, int KIND>
+DEV void ws_group(const Job &J, WsLds &L, const DevTables *T, const LaneConst &LC, uint64_t gs,
+                  uint64_t ge, uint64_t tag) {
+  const uint32_t lane = lane_id();
+  const bool multi = J.n_streams != 1;
+  uint32_t s = J.s0;
+  uint64_t rr = gs;
+  if (multi) {
+    uint64_t v;
+    split(J, gs, s, v);
+    s = uni(s);
+    rr = uni64(v - J.first);
+  }
+  uint32_t bits = 0, sub = 0;
+  uint64_t Sc = 0;
+  bool have = false;
+  for (uint64_t ec = gs; ec < ge; ec += BSTEP, ++sub) {
+    double x[4];
+    float xf[4];
+    uint32_t b4;
+    const bool full = ec + BSTEP <= ge;
+    if (!multi || rr + BSTEP <= J.n_per) {
+      const uint64_t vc = J.first + rr;
+      if (KIND == ZG_JAVA_LCG48 && !have) {
+        Sc = lcg_jump(&T->lcg, lcg_state0(J.seed), 2 * lcg_index(s, vc, 0) + 1);
+        have = true;
+      }
+      if (full)
+        b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
+      else
+        b4 = step_regs<OP, KIND, false>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
+      if (KIND == ZG_JAVA_LCG48) Sc = aff(T->lcg.jump[1][2], Sc);
+    } else {
+      b4 = step_general<OP, KIND>(J, L.t.f64, L.t.f32, T, ec, ge, x, xf);
+      have = false;
+    }
+    if (full)
+      step_store<OP, true>(J, ec, ge, x, xf);
+    else
+      step_store<OP, false>(J, ec, ge, x, xf);
+    bits |= b4 << (4 * sub);
+    rr += BSTEP;
+    if (multi)
+      while (rr >= J.n_per) {
+        rr -= J.n_per;
+        ++s;
+        have = false;
+      }
+  }
+  if (bits) {
+    // the placeholders before their ring entries
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint32_t p = atomicAdd(&L.tail, (uint32_t)__builtin_popcount(bits));
+    do {
+      const uint32_t b = __builtin_ctz(bits);
+      const uint64_t e = gs + (b >> 2) * BSTEP + slot_elem<OP>(0, lane, b & 3);
+      uint64_t *slot = &L.ring[p & (WS_RING - 1)];
+      while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+        __builtin_amdgcn_s_sleep(1);
+      __hip_atomic_store(slot, (tag | e) + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      bits &= bits - 1;
+      ++p;
+    } while (bits);
+  }
+}
+
 // Streaming role: the workgroup's groups in turn (group c of workgroup w is
 // group c * gridDim.x + w of the body that starts at b0, so the workgroups
 // write neighbouring groups at any time), each lane's slow elements published
@@ -1245,72 +1325,12 @@ DEV void ws_stream(const Job &J, WsLds &L, const DevTables *T, const LaneConst &
                    uint64_t b1, uint32_t gsteps) {
   const uint32_t lane = lane_id();
   const uint32_t GE = gsteps * BSTEP;
-  const bool multi = J.n_streams != 1;
   for (;;) {
     uint32_t g = 0;
     if (lane == 0) g = atomicAdd(&L.next, 1u);
     const uint64_t gs = b0 + ((uint64_t)uni(g) * gridDim.x + blockIdx.x) * GE;
     if (gs >= b1) break;
-    const uint64_t ge = gs + GE < b1 ? gs + GE : b1;
-    uint32_t s = J.s0;
-    uint64_t rr = gs;
-    if (multi) {
-      uint64_t v;
-      split(J, gs, s, v);
-      s = uni(s);
-      rr = uni64(v - J.first);
-    }
-    uint32_t bits = 0, sub = 0;
-    uint64_t Sc = 0;
-    bool have = false;
-    for (uint64_t ec = gs; ec < ge; ec += BSTEP, ++sub) {
-      double x[4];
-      float xf[4];
-      uint32_t b4;
-      const bool full = ec + BSTEP <= ge;
-      if (!multi || rr + BSTEP <= J.n_per) {
-        const uint64_t vc = J.first + rr;
-        if (KIND == ZG_JAVA_LCG48 && !have) {
-          Sc = lcg_jump(&T->lcg, lcg_state0(J.seed), 2 * lcg_index(s, vc, 0) + 1);
-          have = true;
-        }
-        if (full)
-          b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
-        else
-          b4 = step_regs<OP, KIND, false>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
-        if (KIND == ZG_JAVA_LCG48) Sc = aff(T->lcg.jump[1][2], Sc);
-      } else {
-        b4 = step_general<OP, KIND>(J, L.t.f64, L.t.f32, T, ec, ge, x, xf);
-        have = false;
-      }
-      if (full)
-        step_store<OP, true>(J, ec, ge, x, xf);
-      else
-        step_store<OP, false>(J, ec, ge, x, xf);
-      bits |= b4 << (4 * sub);
-      rr += BSTEP;
-      if (multi)
-        while (rr >= J.n_per) {
-          rr -= J.n_per;
-          ++s;
-          have = false;
-        }
-    }
-    if (bits) {
-      // the placeholders before their ring entries
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      uint32_t p = atomicAdd(&L.tail, (uint32_t)__builtin_popcount(bits));
-      do {
-        const uint32_t b = __builtin_ctz(bits);
-        const uint64_t e = gs + (b >> 2) * BSTEP + slot_elem<OP>(0, lane, b & 3);
-        uint64_t *slot = &L.ring[p & (WS_RING - 1)];
-        while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
-          __builtin_amdgcn_s_sleep(1);
-        __hip_atomic_store(slot, e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        bits &= bits - 1;
-        ++p;
-      } while (bits);
-    }
+    ws_group<OP, KIND>(J, L, T, LC, gs, gs + GE < b1 ? gs + GE : b1, 0);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   if (lane == 0) atomicAdd(&L.done, 1u);
@@ -1318,18 +1338,22 @@ DEV void ws_stream(const Job &J, WsLds &L, const DevTables *T, const LaneConst &
 
 // A round over the last n (<= 64) entries of a drain wave's retry queue,
 // one per lane, each finished by resolve from its recorded draw.
-template <int OP, int KIND>
-DEV void ws_retry(const Job &J, const LdsTabs &L, const DevTables *T, double r, uint32_t dmax,
-                  const uint64_t *rq, uint32_t base, uint32_t n, bool &budget) {
+// BATCH: entries name their request, whose job the lane reads (R).
+template <int OP, int KIND, bool BATCH>
+DEV void ws_retry(const Job &J0, const DevRequest *R, const LdsTabs &L, const DevTables *T,
+                  double r, uint32_t dmax, const uint64_t *rq, uint32_t base, uint32_t n,
+                  bool &budget) {
   const uint32_t lane = lane_id();
   if (lane < n) {
     const uint64_t ent = rq[base + lane];
-    const uint64_t e = ent & ENT_E;
+    const uint64_t e = BATCH ? ent & WSB_EMASK : ent & ENT_E;
+    const uint32_t d = BATCH ? (uint32_t)(ent >> WSB_E) & ((1u << (WSB_R - WSB_E)) - 1)
+                             : (uint32_t)(ent >> ENT_D);
+    const Job J = BATCH ? R[ent >> WSB_R].job : J0;
     uint32_t s;
     uint64_t v;
     split(J, e, s, v);
-    patch_store<OP>(J, e, resolve<OP, KIND>(J, L, T, r, dmax, s, v, budget,
-                                            (uint32_t)(ent >> ENT_D)));
+    patch_store<OP>(J, e, resolve<OP, KIND>(J, L, T, r, dmax, s, v, budget, d));
   }
 }
 
@@ -1338,9 +1362,9 @@ DEV void ws_retry(const Job &J, const LdsTabs &L, const DevTables *T, double r, 
 // are claimed.  Each entry gets its first drain step; the few it leaves
 // undecided (and the base-strip attempts) go to the wave's own retry queue,
 // which is finished 64 at a time, the rest at the end.
-template <int OP, int KIND>
-DEV void ws_drain(const Job &J, WsLds &L, const DevTables *T, double r, uint32_t dmax,
-                  uint32_t n_stream, uint32_t slot_id, bool &budget) {
+template <int OP, int KIND, bool BATCH>
+DEV void ws_drain(const Job &J0, const DevRequest *R, WsLds &L, const DevTables *T, double r,
+                  uint32_t dmax, uint32_t n_stream, uint32_t slot_id, bool &budget) {
   const uint32_t lane = lane_id();
   uint64_t *rq = L.rq[slot_id];
   uint32_t rn = 0;   // wave-uniform
@@ -1368,7 +1392,9 @@ DEV void ws_drain(const Job &J, WsLds &L, const DevTables *T, double r, uint32_t
         __builtin_amdgcn_s_sleep(1);
       __hip_atomic_store(slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      const uint64_t e = ent - 1;
+      const uint64_t x = ent - 1;
+      const uint64_t e = BATCH ? x & WSB_EMASK : x;
+      const Job J = BATCH ? R[x >> WSB_E].job : J0;
       uint32_t s;
       uint64_t v;
       split(J, e, s, v);
@@ -1378,7 +1404,8 @@ DEV void ws_drain(const Job &J, WsLds &L, const DevTables *T, double r, uint32_t
         patch_store<OP>(J, e, z);
       } else {
         und = true;
-        rent = e | ((uint64_t)d << ENT_D);
+        rent = BATCH ? e | ((uint64_t)d << WSB_E) | ((x >> WSB_E) << WSB_R)
+                     : e | ((uint64_t)d << ENT_D);
       }
     }
     // undecided: to this wave's retry queue (rn < 64 before, so it fits)
@@ -1390,14 +1417,14 @@ DEV void ws_drain(const Job &J, WsLds &L, const DevTables *T, double r, uint32_t
     }
     if (rn >= 64) {
       rn -= 64;
-      ws_retry<OP, KIND>(J, L.t, T, r, dmax, rq, rn, 64, budget);
+      ws_retry<OP, KIND, BATCH>(J0, R, L.t, T, r, dmax, rq, rn, 64, budget);
       __builtin_amdgcn_wave_barrier();
     }
   }
   while (rn) {
     const uint32_t m = rn < 64 ? rn : 64;
     rn -= m;
-    ws_retry<OP, KIND>(J, L.t, T, r, dmax, rq, rn, m, budget);
+    ws_retry<OP, KIND, BATCH>(J0, R, L.t, T, r, dmax, rq, rn, m, budget);
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -1436,7 +1463,7 @@ __global__ __launch_bounds__(1024) void k_zigws(Job J, const DevTables *__restri
     // streaming waves wait on it; one step of priority keeps the drain ahead
     // (the streaming waves still fill the store pipe).
     __builtin_amdgcn_s_setprio(1);
-    ws_drain<OP, KIND>(J, L, T, r, dmax, n_stream, wave - n_stream, budget);
+    ws_drain<OP, KIND, false>(J, nullptr, L, T, r, dmax, n_stream, wave - n_stream, budget);
   }
   __syncthreads();
   // the elements before the first aligned one
@@ -1780,6 +1807,81 @@ __global__ __launch_bounds__(1024) void k_bzig(DevRequest *R, const BatchHeader 
   }
   if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane_id() == 0)
     raise_flag(flags, ZG_FLAG_BUDGET);
+}
+
+// Batch work of one ziggurat class, wave-specialised: a persistent grid, each
+// workgroup's first (waves - ws_drain) waves take (item, group) units from an
+// LDS counter (item i of workgroup w is the class's item w + i gridDim.x, a
+// request tile of tile x waves elements, cut into groups of ws_gsteps steps)
+// and stream them as the plain wave-specialised fill does, publishing slow
+// elements with their request; the last ws_drain waves resolve and patch
+// them, reading each entry's job from its request.  A request's elements
+// before its first aligned one are resolved by the wave that streams its
+// first group.
+template <int OP, int KIND>
+__global__ __launch_bounds__(1024) void k_bzigws(DevRequest *R, const BatchHeader *H,
+                                                 const DevTables *__restrict__ T,
+                                                 uint32_t *flags) {
+  constexpr int C = batch_class(OP, KIND);
+  const uint32_t cnt = H->cls_cnt[C];
+  if (blockIdx.x >= cnt) return;
+  __shared__ WsLds L;
+  load_tabs<OP>(T, L.t);
+  for (uint32_t i = threadIdx.x; i < WS_RING; i += blockDim.x) L.ring[i] = 0;
+  if (threadIdx.x == 0) {
+    L.next = 0;
+    L.tail = 0;
+    L.head = 0;
+    L.done = 0;
+  }
+  __syncthreads();
+  const double r = T->r;
+  const uint32_t dmax = H->dmax;
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t n_stream = nw - H->ws_drain;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const uint32_t lane = lane_id();
+  bool budget = false;
+  if (wave < n_stream) {
+    const LaneConst LC = lane_constants<OP, KIND>(T);
+    const uint64_t *items = (const uint64_t *)((const char *)H + H->items_off);
+    const uint32_t off = H->cls_off[C];
+    const uint32_t G = H->cls_groups[C];
+    const uint64_t GE = (uint64_t)H->ws_gsteps * BSTEP;
+    for (;;) {
+      uint32_t u = 0;
+      if (lane == 0) u = atomicAdd(&L.next, 1u);
+      u = uni(u);
+      const uint32_t i = u / G, g = u - i * G;
+      const uint64_t k = blockIdx.x + (uint64_t)i * gridDim.x;
+      if (k >= cnt) break;
+      const uint64_t it = items[off + k];
+      const uint32_t ri = uni((uint32_t)(it >> 32)), j = uni((uint32_t)it);
+      const DevRequest &rq = R[ri];
+      if (rq.status != 0) continue;
+      const Job J = rq.job;
+      const uint64_t t0 = rq.head + (uint64_t)j * rq.tile * nw;
+      const uint64_t t1 = t0 + (uint64_t)rq.tile * nw < J.n_total ? t0 + (uint64_t)rq.tile * nw
+                                                                  : J.n_total;
+      if (j == 0 && g == 0 && lane < rq.head) {
+        uint32_t se;
+        uint64_t ve;
+        split(J, lane, se, ve);
+        patch_store<OP>(J, lane, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
+      }
+      const uint64_t gs = t0 + g * GE;
+      if (gs >= t1) continue;
+      ws_group<OP, KIND>(J, L, T, LC, gs, gs + GE < t1 ? gs + GE : t1, (uint64_t)ri << WSB_E);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) atomicAdd(&L.done, 1u);
+  } else {
+    // drain waves ahead of the ring, as in the plain wave-specialised fill
+    __builtin_amdgcn_s_setprio(1);
+    const Job none{};
+    ws_drain<OP, KIND, true>(none, R, L, T, r, dmax, n_stream, wave - n_stream, budget);
+  }
+  if (__builtin_amdgcn_ballot_w64(budget) != 0 && lane == 0) raise_flag(flags, ZG_FLAG_BUDGET);
 }
 
 // Batch work of the polar class: every wave of a workgroup tile runs the
@@ -2323,16 +2425,66 @@ hipError_t launch_decide(const uint64_t *words, uint64_t n, const DevTables *T, 
 const void *kernel_reserve() { return (const void *)k_reserve; }
 const void *kernel_complete() { return (const void *)k_complete; }
 
-const void *kernel_batch_class(int cls) {
+const void *kernel_batch_class(int cls, bool ws) {
   switch (cls) {
-    case batch_class(OP_ZIG64, ZG_SPLITMIX64): return (const void *)k_bzig<OP_ZIG64, ZG_SPLITMIX64>;
-    case batch_class(OP_ZIG64, ZG_JAVA_LCG48): return (const void *)k_bzig<OP_ZIG64, ZG_JAVA_LCG48>;
-    case batch_class(OP_ZIG32, ZG_SPLITMIX64): return (const void *)k_bzig<OP_ZIG32, ZG_SPLITMIX64>;
-    case batch_class(OP_ZIG32, ZG_JAVA_LCG48): return (const void *)k_bzig<OP_ZIG32, ZG_JAVA_LCG48>;
-    case batch_class(OP_MUTATE, ZG_SPLITMIX64): return (const void *)k_bzig<OP_MUTATE, ZG_SPLITMIX64>;
-    case batch_class(OP_MUTATE, ZG_JAVA_LCG48): return (const void *)k_bzig<OP_MUTATE, ZG_JAVA_LCG48>;
+    case batch_class(OP_ZIG64, ZG_SPLITMIX64):
+      return ws ? (const void *)k_bzigws<OP_ZIG64, ZG_SPLITMIX64>
+                : (const void *)k_bzig<OP_ZIG64, ZG_SPLITMIX64>;
+    case batch_class(OP_ZIG64, ZG_JAVA_LCG48):
+      return ws ? (const void *)k_bzigws<OP_ZIG64, ZG_JAVA_LCG48>
+                : (const void *)k_bzig<OP_ZIG64, ZG_JAVA_LCG48>;
+    case batch_class(OP_ZIG32, ZG_SPLITMIX64):
+      return ws ? (const void *)k_bzigws<OP_ZIG32, ZG_SPLITMIX64>
+                : (const void *)k_bzig<OP_ZIG32, ZG_SPLITMIX64>;
+    case batch_class(OP_ZIG32, ZG_JAVA_LCG48):
+      return ws ? (const void *)k_bzigws<OP_ZIG32, ZG_JAVA_LCG48>
+                : (const void *)k_bzig<OP_ZIG32, ZG_JAVA_LCG48>;
+    case batch_class(OP_MUTATE, ZG_SPLITMIX64):
+      return ws ? (const void *)k_bzigws<OP_MUTATE, ZG_SPLITMIX64>
+                : (const void *)k_bzig<OP_MUTATE, ZG_SPLITMIX64>;
+    case batch_class(OP_MUTATE, ZG_JAVA_LCG48):
+      return ws ? (const void *)k_bzigws<OP_MUTATE, ZG_JAVA_LCG48>
+                : (const void *)k_bzig<OP_MUTATE, ZG_JAVA_LCG48>;
     case batch_class(OP_POLAR, ZG_SPLITMIX64): return (const void *)k_bpolar<ZG_SPLITMIX64>;
     default: return (const void *)k_bpolar<ZG_JAVA_LCG48>;
+  }
+}
+
+template <int OP, int KIND>
+static hipError_t launch_bz(bool ws, dim3 g, dim3 b, DevRequest *R, const BatchHeader *H,
+                            const DevTables *T, uint32_t *flags, hipStream_t stream) {
+  if (ws)
+    hipLaunchKernelGGL((k_bzigws<OP, KIND>), g, b, 0, stream, R, H, T, flags);
+  else
+    hipLaunchKernelGGL((k_bzig<OP, KIND>), g, b, 0, stream, R, H, T, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_class(int cls, bool ws, uint32_t grid, uint32_t waves, DevRequest *R,
+                              const BatchHeader *H, const DevTables *T, uint32_t *flags,
+                              hipStream_t stream) {
+  const dim3 g(grid), b(64 * waves);
+  switch (cls) {
+    case batch_class(OP_ZIG64, ZG_SPLITMIX64):
+      return launch_bz<OP_ZIG64, ZG_SPLITMIX64>(ws, g, b, R, H, T, flags, stream);
+    case batch_class(OP_ZIG64, ZG_JAVA_LCG48):
+      return launch_bz<OP_ZIG64, ZG_JAVA_LCG48>(ws, g, b, R, H, T, flags, stream);
+    case batch_class(OP_ZIG32, ZG_SPLITMIX64):
+      return launch_bz<OP_ZIG32, ZG_SPLITMIX64>(ws, g, b, R, H, T, flags, stream);
+    case batch_class(OP_ZIG32, ZG_JAVA_LCG48):
+      return launch_bz<OP_ZIG32, ZG_JAVA_LCG48>(ws, g, b, R, H, T, flags, stream);
+    case batch_class(OP_MUTATE, ZG_SPLITMIX64):
+      return launch_bz<OP_MUTATE, ZG_SPLITMIX64>(ws, g, b, R, H, T, flags, stream);
+    case batch_class(OP_MUTATE, ZG_JAVA_LCG48):
+      return launch_bz<OP_MUTATE, ZG_JAVA_LCG48>(ws, g, b, R, H, T, flags, stream);
+    case batch_class(OP_POLAR, ZG_SPLITMIX64):
+      hipLaunchKernelGGL(k_bpolar<ZG_SPLITMIX64>, g, b, batch_class_lds_bytes(cls, waves), stream,
+                         R, H, T, flags);
+      return hipGetLastError();
+    default:
+      hipLaunchKernelGGL(k_bpolar<ZG_JAVA_LCG48>, g, b, batch_class_lds_bytes(cls, waves), stream,
+                         R, H, T, flags);
+      return hipGetLastError();
   }
 }
 

@@ -183,10 +183,14 @@ extern "C" zg_status zg_autotune(zg_ctx *ctx, const char *cache_path, uint64_t b
     float best_ms = 1e30f;
     const uint32_t btiles[] = {1024, 2048, 4096};
     const uint32_t bpc[] = {1, 2, 4};
+    // block-pooled (no drain waves) and wave-specialised (a quarter of the
+    // waves drain) class kernels
     for (uint32_t tl : btiles)
-      for (uint32_t w : {4u, 8u})
-        for (uint32_t k : bpc) {
-          zg_tune cand = {tl, w, k, 0, 0, 4};
+      for (uint32_t w : {4u, 8u, 16u})
+        for (uint32_t k : bpc)
+          for (uint32_t dw : {0u, w / 4}) {
+          if (w == 16 && dw == 0) continue;
+          zg_tune cand = {tl, w, k, 0, dw, 4};
           st = zg_set_tune(ctx, ZG_TUNE_BATCH, &cand);
           if (st != ZG_OK) break;
           auto run = [&]() { zg_batch(ctx, reqs.data(), (uint32_t)reqs.size(), nullptr, s); };

@@ -12,6 +12,15 @@
 //     with the output HEAD elements past a 16-byte boundary, by the pooled
 //     kernel (NDRAIN 0) or the wave-specialised one with NDRAIN drain waves,
 //     GSTEPS steps per group; writes the values.
+//   kernel_emu batch WS WAVES NDRAIN GSTEPS TILE GRID SPEC OUTFILE INFILE
+//     one batch class kernel (launch_batch_class), wave-specialised (WS 1,
+//     NDRAIN drain waves, GSTEPS steps per group) or block-pooled (WS 0),
+//     WAVES waves per workgroup, TILE elements per wave (twice for FP32), a
+//     grid of GRID workgroups, over the requests of SPEC (lines: op kind n
+//     seed stream head; one class), each output HEAD elements before a 16-byte
+//     boundary; mutation requests start from INFILE's doubles in request
+//     order.  The header, requests and items are laid out as zg_batch lays
+//     them out; writes every request's values in request order.
 #include "hip/hip_runtime.h"
 
 #include <algorithm>
@@ -198,6 +207,95 @@ static int fill_only(char **a) {
   return 0;
 }
 
+static int batch_only(char **a) {
+  const bool ws = atoi(a[0]) != 0;
+  const uint32_t waves = (uint32_t)atoi(a[1]), n_drain = (uint32_t)atoi(a[2]);
+  const uint32_t gsteps = (uint32_t)atoi(a[3]), tile = (uint32_t)atoi(a[4]);
+  const uint32_t grid = (uint32_t)atoi(a[5]);
+  FILE *sp = fopen(a[6], "r");
+  if (!sp) return 3;
+  struct Spec {
+    uint32_t op, kind;
+    uint64_t n, seed;
+    uint32_t stream, head;
+  };
+  std::vector<Spec> sv;
+  Spec x;
+  while (fscanf(sp, "%u %u %llu %llu %u %u", &x.op, &x.kind, (unsigned long long *)&x.n,
+                (unsigned long long *)&x.seed, &x.stream, &x.head) == 6)
+    sv.push_back(x);
+  fclose(sp);
+  if (sv.empty()) return 2;
+  const int c = batch_class(sv[0].op, sv[0].kind);
+  FILE *in = sv[0].op == OP_MUTATE ? fopen(a[8], "rb") : nullptr;
+  std::vector<char *> bases;
+  std::vector<DevRequest> reqs;
+  std::vector<uint64_t> items;
+  for (size_t k = 0; k < sv.size(); ++k) {
+    const Spec &q = sv[k];
+    if (batch_class(q.op, q.kind) != c || q.n == 0) return 2;
+    const size_t esz = q.op == OP_ZIG32 ? 4 : 8;
+    const uint32_t per16 = (uint32_t)(16 / esz);
+    if (q.head >= per16) return 2;
+    const size_t lead = (per16 - q.head) % per16;
+    char *base = (char *)malloc((q.n + lead) * esz);   // exact: ASan sees any overrun
+    if (((uintptr_t)base) % 16) return 5;
+    bases.push_back(base);
+    void *out = base + lead * esz;
+    if (q.op == OP_MUTATE && (!in || fread(out, 8, q.n, in) != q.n)) return 3;
+    DevRequest d{};
+    d.job = Job{out, q.n, q.n, 0, q.seed, 0.1, 1.0 / (double)q.n, q.stream, 1, q.kind, q.op};
+    d.handle = ZG_NO_HANDLE;
+    d.limit = q.kind == ZG_JAVA_LCG48 ? ZG_LCG_WINDOW : ZG_SM64_WINDOW;
+    const uint32_t wave_tile = q.op == OP_ZIG32 ? 2 * tile : tile;
+    d.tile = (wave_tile + 255) / 256 * 256;
+    const uint32_t h = q.op == OP_ZIG32 ? (uint32_t)((4 - (((uintptr_t)out >> 2) & 3)) & 3)
+                                        : (uint32_t)(((uintptr_t)out >> 3) & 1);
+    d.head = (uint32_t)std::min<uint64_t>(h, q.n);
+    const uint64_t per = (uint64_t)d.tile * waves;
+    uint64_t tiles = (q.n - d.head + per - 1) / per;
+    if (tiles == 0) tiles = 1;
+    d.tiles = (uint32_t)tiles;
+    for (uint32_t j = 0; j < d.tiles; ++j) items.push_back(((uint64_t)k << 32) | j);
+    reqs.push_back(d);
+  }
+  if (in) fclose(in);
+  // header, requests, items: one buffer, as a batch slot holds them
+  const size_t items_off = sizeof(BatchHeader) + reqs.size() * sizeof(DevRequest);
+  char *buf = (char *)calloc(1, items_off + items.size() * sizeof(uint64_t));
+  BatchHeader *H = (BatchHeader *)buf;
+  DevRequest *R = (DevRequest *)(buf + sizeof(BatchHeader));
+  H->nreq = (uint32_t)reqs.size();
+  H->dmax = ZG_MAX_DRAWS;
+  H->n_items = (uint32_t)items.size();
+  H->items_off = (uint32_t)items_off;
+  H->cls_off[c] = 0;
+  H->cls_cnt[c] = (uint32_t)items.size();
+  H->ws_drain = ws ? n_drain : 0;
+  H->ws_gsteps = gsteps;
+  const uint64_t per = (uint64_t)reqs[0].tile * waves, ge = 256ull * gsteps;
+  H->cls_groups[c] = (uint32_t)((per + ge - 1) / ge);
+  std::memcpy(R, reqs.data(), reqs.size() * sizeof(DevRequest));
+  std::memcpy(buf + items_off, items.data(), items.size() * sizeof(uint64_t));
+  DevTables *T = host_tables();
+  uint32_t *flags = (uint32_t *)calloc(1, sizeof(uint32_t));
+  std::fprintf(stderr, "batch class=%d requests=%zu items=%zu ws=%d groups=%u\n", c, reqs.size(),
+               items.size(), (int)ws, H->cls_groups[c]);
+  if (launch_batch_class(c, ws, grid, waves, R, H, T, flags, nullptr) != hipSuccess) return 4;
+  FILE *f = fopen(a[7], "wb");
+  if (!f) return 3;
+  for (size_t k = 0; k < reqs.size(); ++k)
+    fwrite(reqs[k].job.out, sv[k].op == OP_ZIG32 ? 4 : 8, sv[k].n, f);
+  fclose(f);
+  std::fprintf(stderr, "flags=%u\n", *flags);
+  for (char *b : bases) free(b);
+  free(buf);
+  free(flags);
+  delete T;
+  pools.clear();
+  return 0;
+}
+
 // ea POP GENES K SEED STREAM GEN RATE SIGMA LO HI PARENTS FITNESS CHILDREN WINNERS:
 // one EA generation (launch_ea) from float64 files, outputs to files.
 static int ea_only(char **a) {
@@ -248,6 +346,7 @@ static int ea_only(char **a) {
 
 int main(int argc, char **argv) {
   if (argc >= 16 && std::strcmp(argv[1], "ea") == 0) return ea_only(argv + 2);
+  if (argc >= 11 && std::strcmp(argv[1], "batch") == 0) return batch_only(argv + 2);
   if (argc == 4 && std::strcmp(argv[1], "scan") == 0)
     return scan_only((uint32_t)strtoul(argv[2], 0, 10), strtoull(argv[3], 0, 10));
   if (argc >= 13 && std::strcmp(argv[1], "fill") == 0) return fill_only(argv + 2);

@@ -87,7 +87,14 @@ static char tag_reserve, tag_complete, tag_class[BATCH_CLASSES];
 
 const void *kernel_reserve() { return &tag_reserve; }
 const void *kernel_complete() { return &tag_complete; }
-const void *kernel_batch_class(int cls) { return &tag_class[cls]; }
+const void *kernel_batch_class(int cls, bool) { return &tag_class[cls]; }
+// a direct class launch: the same tagged launch on the stream, in its order
+hipError_t launch_batch_class(int cls, bool, uint32_t grid, uint32_t waves, DevRequest *R,
+                              const BatchHeader *H, const DevTables *T, uint32_t *flags,
+                              hipStream_t stream) {
+  void *args[] = {&R, &H, &T, &flags};
+  return hipLaunchKernel(&tag_class[cls], dim3(grid), dim3(64 * waves), args, 0, stream);
+}
 size_t batch_class_lds_bytes(int, uint32_t) { return 0; }
 
 // The plain paths are not part of this harness.

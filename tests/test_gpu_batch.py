@@ -73,17 +73,19 @@ def test_batch_equals_plain_calls_and_shapes(ctx, zg):
     ref = [host(r["out"]).copy() for r in reqs]
     saved = {c: ctx.zg_get_tune(c) for c in range(zg.ZG_TUNE_CLASSES)}
     try:
-        shapes = [(1024, 4, 1), (2048, 8, 2), (4096, 16, 4), (8192, 2, 1)]
-        for tile, waves, bpc in shapes:
+        # the batch classes block-pooled (0 drain waves) or wave-specialised
+        shapes = [(1024, 4, 1, 1), (2048, 8, 2, 0), (4096, 16, 4, 2), (8192, 2, 1, 0),
+                  (2048, 16, 1, 4), (1024, 8, 3, 7)]
+        for tile, waves, bpc, bdrain in shapes:
             for c in (0, 2, 3):
                 ctx.zg_set_tune(c, tile, waves, bpc)
             ctx.zg_set_tune(1, 2 * tile, waves, bpc)
-            ctx.zg_set_tune(4, max(tile // 2, 256), min(waves, 8), bpc)
+            ctx.zg_set_tune(4, max(tile // 2, 256), min(waves, 8), bpc, 0, bdrain, 2)
             for r, want in zip(reqs, ref):
                 r["out"].fill_(float("nan"))
             ctx.zg_batch(reqs)
             for r, want in zip(reqs, ref):
-                assert host(r["out"]).tobytes() == want.tobytes(), (tile, waves, bpc)
+                assert host(r["out"]).tobytes() == want.tobytes(), (tile, waves, bpc, bdrain)
             for r, want in zip(reqs, ref):
                 r["out"].fill_(float("nan"))
                 o = r["out"]
