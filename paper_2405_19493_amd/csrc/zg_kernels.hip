@@ -1858,7 +1858,13 @@ __global__ __launch_bounds__(1024) void k_bzigws(DevRequest *R, const BatchHeade
       const uint64_t it = items[off + k];
       const uint32_t ri = uni((uint32_t)(it >> 32)), j = uni((uint32_t)it);
       const DevRequest &rq = R[ri];
-      if (rq.status != 0) continue;
+      // the item's remaining groups are empty from here (a skipped request,
+      // or past the tile's end): the counter moves on to the next item
+      const uint32_t next_item = (i + 1) * G;
+      if (rq.status != 0) {
+        if (lane == 0) atomicMax(&L.next, next_item);
+        continue;
+      }
       const Job J = rq.job;
       const uint64_t t0 = rq.head + (uint64_t)j * rq.tile * nw;
       const uint64_t t1 = t0 + (uint64_t)rq.tile * nw < J.n_total ? t0 + (uint64_t)rq.tile * nw
@@ -1870,7 +1876,10 @@ __global__ __launch_bounds__(1024) void k_bzigws(DevRequest *R, const BatchHeade
         patch_store<OP>(J, lane, resolve<OP, KIND>(J, L.t, T, r, dmax, se, ve, budget));
       }
       const uint64_t gs = t0 + g * GE;
-      if (gs >= t1) continue;
+      if (gs >= t1) {
+        if (lane == 0) atomicMax(&L.next, next_item);
+        continue;
+      }
       ws_group<OP, KIND>(J, L, T, LC, gs, gs + GE < t1 ? gs + GE : t1, (uint64_t)ri << WSB_E);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

@@ -114,6 +114,13 @@ inline uint32_t emu_mbcnt_hi(uint32_t m, uint32_t a) { uint32_t l = threadIdx.x 
 inline uint32_t atomicAdd(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline int32_t atomicAdd(int32_t *p, int32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline uint32_t atomicOr(uint32_t *p, uint32_t v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline uint32_t atomicMax(uint32_t *p, uint32_t v) {
+  uint32_t cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (cur < v &&
+         !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+  }
+  return cur;
+}
 inline int32_t atomicSub(int32_t *p, int32_t v) { return __atomic_fetch_sub(p, v, __ATOMIC_SEQ_CST); }
 inline uint32_t atomicCAS(uint32_t *p, uint32_t cmp, uint32_t val) {
   __atomic_compare_exchange_n(p, &cmp, val, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
