@@ -157,6 +157,7 @@ def cpu_baseline(seconds):
                         cpu[key] = val
     except OSError:
         pass
+    rows = cpu_rows(orc, cores)
     return {"value": done / dt, "unit": "variates/s", "cores": cores, "kind": "oracle",
             "cpu": cpu.get("model name", ""), "cpu_id": cpu,
             "nproc": os.cpu_count(),
@@ -167,7 +168,41 @@ def cpu_baseline(seconds):
                       f"(SplitMix64 seed 7): {done} variates in {dt:.1f} s",
             "one_core": {"value": k * N_PER / dt1, "unit": "variates/s",
                          "ns_per_variate": dt1 * 1e9 / (k * N_PER),
-                         "sample": f"streams 0..{k - 1}, one thread"}}
+                         "sample": f"streams 0..{k - 1}, one thread"},
+            "rows": rows}
+
+
+def cpu_rows(orc, cores):
+    """The oracle on a bounded sample of each other row's workload, with the
+    same threads: rates to set beside the GPU rows."""
+    import numpy as np
+    out = {}
+
+    def timed(name, fn, units, unit, sample):
+        t0 = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t0
+        out[name] = {"value": units / dt, "unit": unit, "cores": cores, "sample": sample,
+                     "seconds": dt}
+
+    ns = 16384   # a quarter of the 65536 streams of 4096
+    timed("mcfarland", lambda: orc.fill_streams_mz(orc.SM64, SEED, 0, ns, 0, N_PER, nthreads=cores),
+          ns * N_PER, "variates/s", f"modified ziggurat, streams 0..{ns - 1} x 4096, seed 7")
+    timed("polar", lambda: orc.fill_streams_polar(orc.SM64, SEED, 0, ns, 0, N_PER, nthreads=cores),
+          ns * N_PER, "variates/s", f"polar, streams 0..{ns - 1} x 4096, seed 7")
+    timed("f32", lambda: orc.fill_streams_f32(orc.SM64, SEED, 0, ns, 0, N_PER, nthreads=cores),
+          ns * N_PER, "variates/s", f"FP32 ziggurat, streams 0..{ns - 1} x 4096, seed 7")
+    n_lcg = 1 << 26
+    timed("c3_lcg", lambda: orc.fill_f64(orc.LCG48, 123456789, 0, 0, n_lcg, nthreads=cores),
+          n_lcg, "variates/s", "FP64 ziggurat, LCG48 seed 123456789, the first 2^26 of the stream")
+    pop, genes = 16384, 1024
+    g = np.random.Generator(np.random.PCG64(7))
+    P = g.uniform(-5.0, 5.0, (pop, genes))
+    F = (P * P).sum(axis=1)
+    timed("ea_step", lambda: orc.ea_step(P, F, 2, 2024, 100, 3, 0.05, 0.1, -5.0, 5.0,
+                                         nthreads=cores),
+          pop * genes, "genes/s", "one EA generation, 16384 x 1024 genes (the whole row)")
+    return out
 
 
 def c3_lcg(ctx, Z, torch, steps, warmup):
