@@ -416,11 +416,15 @@ zg_status zg_fill_each(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq, void 
  * drain_waves: 0 runs the plain ziggurat fills (FP64, FP32, mutation) with
  * the block-pooled kernel (streaming, one barrier, a drain of the pooled
  * slow elements, per workgroup tile), 1..8 with the wave-specialised kernel
- * (one 16-wave workgroup per CU, drain_waves of whose waves resolve the slow
- * elements the others publish in an LDS ring; tile, waves_per_block,
- * batch_blocks_per_cu and queue_cap then do not apply), and group_steps: the
+ * (persistent workgroups of waves_per_block waves, batch_blocks_per_cu of
+ * them per CU at most (at least one, capped by occupancy), drain_waves of
+ * whose waves, at most waves_per_block - 1, resolve the slow elements the
+ * others publish in an LDS ring; tile and queue_cap then do not apply; for
+ * the batch class, drain_waves selects the wave-specialised class kernels
+ * with the same meaning), and group_steps: the
  * 256-element steps a wave streams between queue appends (1, 2, 4 or 8; the
- * plain ziggurat fills only).  Any shape gives the same bits. */
+ * plain ziggurat fills and the wave-specialised batch class kernels).  Any
+ * shape gives the same bits. */
 typedef struct zg_tune {
   uint32_t tile;
   uint32_t waves_per_block;

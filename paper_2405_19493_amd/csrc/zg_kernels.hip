@@ -2304,16 +2304,25 @@ static hipError_t launch_fill_op(const Job &J, const DevTables *T, uint32_t dmax
   if (gsteps < 1 || gsteps > 8) gsteps = BGROUP;
   if constexpr (OP != OP_POLAR) {
     if (n_drain > 0) {
-      // wave-specialised: one 16-wave workgroup per CU, each owning an equal
-      // range of whole groups
+      // wave-specialised: a persistent grid of `resident` workgroups of
+      // `waves` waves per CU (at least one, capped by occupancy), at least one
+      // streaming wave each; the workgroups take whole groups in turn
       int dev = 0, cus = 256;
       (void)hipGetDevice(&dev);
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      const uint32_t nw = 16;
+      const uint32_t nw = waves < 2 ? 2u : (waves > 16 ? 16u : waves);
       if (n_drain > WS_MAX_DRAIN) n_drain = WS_MAX_DRAIN;
+      if (n_drain > nw - 1) n_drain = nw - 1;
+      int occ = 0;
+      uint32_t per_cu = resident ? resident : 1u;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_zigws<OP, KIND>,
+                                                       (int)(64 * nw), 0) == hipSuccess &&
+          occ > 0 && (uint32_t)occ < per_cu)
+        per_cu = (uint32_t)occ;
       const uint64_t ge = (uint64_t)gsteps * BSTEP;
       const uint64_t groups = (body + ge - 1) / ge;
-      uint64_t blocks = groups < (uint64_t)cus ? (groups ? groups : 1) : (uint64_t)cus;
+      const uint64_t cap = (uint64_t)cus * per_cu;
+      uint64_t blocks = groups < cap ? (groups ? groups : 1) : cap;
       hipLaunchKernelGGL((k_zigws<OP, KIND>), dim3((uint32_t)blocks), dim3(64 * nw), 0, stream, J,
                          T, dmax, flags, head, n_drain, gsteps);
       return hipGetLastError();
