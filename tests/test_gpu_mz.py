@@ -91,7 +91,8 @@ def test_mz_launch_shapes_same_bits(ctx, zg, kind):
         ref = None
         for tile, waves, res, dw, gs in [(1024, 16, 2, 0, 4), (256, 4, 0, 0, 1), (512, 8, 1, 0, 8),
                                          (4096, 16, 0, 0, 2), (1024, 16, 2, 1, 4),
-                                         (1024, 16, 2, 4, 2), (1024, 16, 2, 8, 8)]:
+                                         (1024, 16, 2, 4, 2), (1024, 16, 2, 8, 8),
+                                         (1024, 8, 3, 2, 2), (512, 4, 4, 3, 1)]:
             ctx.zg_set_tune(zg.ZG_TUNE_FILL_MZ, tile, waves, res, 0, dw, gs)
             out = dev_empty(n_per * ns, torch.float64, 1)
             ctx.zg_fill_streams(out, n_per, ns, method=zg.ZG_MCFARLAND, kind=kind, seed=2,

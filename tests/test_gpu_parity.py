@@ -255,8 +255,9 @@ def test_queue_overflow_path(ctx, zg, qcap):
 def test_launch_shape_never_changes_bits(ctx, zg, cls_t, tdt):
     """One workgroup per tile or a persistent grid, small or large tiles,
     4 to 16 waves, 1 to 8 steps per group, the block-pooled or the
-    wave-specialised kernel with 1 to 8 drain waves: the same bits (every
-    variate is keyed by its index)."""
+    wave-specialised kernel with 1 to 8 drain waves, workgroups of 2 to 16
+    waves (down to one streaming wave) and up to 8 per compute unit: the same
+    bits (every variate is keyed by its index)."""
     n = 3 * 65536 + 4097
     saved = ctx.zg_get_tune(cls_t)
     rng = np.random.Generator(np.random.PCG64(12))
@@ -266,7 +267,9 @@ def test_launch_shape_never_changes_bits(ctx, zg, cls_t, tdt):
         for tile, waves, res, dw, gs in [(2048, 16, 2, 0, 4), (256, 4, 0, 0, 1), (512, 8, 1, 0, 8),
                                          (4096, 16, 0, 0, 2), (1024, 16, 4, 0, 4),
                                          (1024, 16, 2, 1, 4), (1024, 16, 2, 4, 2),
-                                         (1024, 16, 2, 8, 8)]:
+                                         (1024, 16, 2, 8, 8), (1024, 8, 3, 2, 2),
+                                         (1024, 12, 2, 3, 4), (512, 4, 4, 3, 1),
+                                         (1024, 2, 8, 1, 2)]:
             ctx.zg_set_tune(cls_t, tile, waves, res, 0, dw, gs)
             out = dev_empty(n, tdt, 1)
             if cls_t == 3:
