@@ -12,6 +12,12 @@
   and is exact on both sides; every value goes through log (1 ulp apart at
   most between the two libraries), a correctly rounded division and square
   root, and a multiply, so every value must be within 4 ulp.
+- Mutated values x = clamp(RN(x0 + RN(sigma z))): a fast-path z is bit-exact,
+  so x is too; a wedge or tail z within 2 ulp of the oracle's moves x by at
+  most 2 |sigma| ulp(z) (the variates' difference, scaled) + 2 ulp(sigma z)
+  (the product's roundings on both sides) + 2 ulp(x) (the sum's), which is
+  many ulps of x when x is much smaller than sigma z.  The clamp only brings
+  values together.
 """
 import numpy as np
 
@@ -84,3 +90,45 @@ def compare(gpu, orc_vals, orc_cls, label="", polar=False):
     assert disagree.size <= DISAGREE_RATE * n, (label, "decision disagreements", rep,
                                                  [(int(i), gpu[i], orc_vals[i], int(orc_cls[i])) for i in disagree[:5]])
     return rep
+
+
+def compare_mutated(gpu, orc_vals, orc_cls, z_of, sigma, label=""):
+    """The rules for mutated values (see the module notes); z_of(indices)
+    gives the oracle's variates z of the given elements (called only for the
+    few slow-path elements whose values differ)."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    orc_vals = np.asarray(orc_vals, dtype=np.float64)
+    n = gpu.size
+    assert orc_vals.size == n
+    eq = gpu.view(np.uint64) == orc_vals.view(np.uint64)
+    path = orc_cls & 3
+    fast = path == 0
+    bad_fast = np.flatnonzero(fast & ~eq)
+    assert bad_fast.size == 0, (label, "fast-path mismatch",
+                                [(int(i), gpu[i], orc_vals[i]) for i in bad_fast[:5]])
+    nan_both = np.isnan(gpu) & np.isnan(orc_vals)
+    budget = np.flatnonzero((path == 3) & ~nan_both)
+    assert budget.size == 0, (label, "budget NaN mismatch", budget[:10].tolist())
+    diff = np.flatnonzero((path != 0) & (path != 3) & ~eq & ~nan_both)
+    if diff.size == 0:
+        return dict(n=n, exact=int(eq.sum()), differ=0, disagreements=0)
+    z = np.asarray(z_of(diff), dtype=np.float64)
+    # each rounding may fall on either side of a binade edge: 2 ulp per rounding
+    bound = (2.0 * abs(sigma) * np.spacing(np.abs(z)) + 2.0 * np.spacing(np.abs(sigma * z)) +
+             2.0 * np.spacing(np.abs(orc_vals[diff])))
+    within = np.abs(gpu[diff] - orc_vals[diff]) <= bound
+    disagree = diff[~within]
+    rep = dict(n=n, exact=int(eq.sum()), differ=int(diff.size), disagreements=int(disagree.size),
+               worst_over_bound=float((np.abs(gpu[diff] - orc_vals[diff]) / bound).max()))
+    assert disagree.size <= DISAGREE_RATE * n, (label, "decision disagreements", rep,
+                                                 [(int(i), gpu[i], orc_vals[i], int(orc_cls[i]))
+                                                  for i in disagree[:5]])
+    return rep
+
+
+def mutation_z(orc, kind, seed, s, first):
+    """z_of for a mutation keyed (kind, seed, stream s, first index): element
+    i was moved by the oracle's FP64 ziggurat variate first + i."""
+    def z_of(idx):
+        return np.array([orc.fill_f64(kind, seed, s, first + int(i), 1)[0][0] for i in idx])
+    return z_of

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from oracle import coracle as orc
-from parity import compare
+from parity import compare, compare_mutated, mutation_z
 
 pytestmark = pytest.mark.gpu
 
@@ -60,8 +60,13 @@ def test_batch_matches_oracle(ctx, zg, count, seed):
     torch.cuda.synchronize()
     for i, r in enumerate(reqs):
         want, cls, polar = _oracle_for(r)
-        compare(host(r["out"]), want, cls, ("batch", i, r["n"], r["dtype"], r["method"], r["kind"]),
-                polar=polar)
+        label = ("batch", i, r["n"], r["dtype"], r["method"], r["kind"])
+        if r.get("op", 0) == 1:
+            compare_mutated(host(r["out"]), want, cls,
+                            mutation_z(orc, r["kind"], r["seed"], r["stream"], r["first_index"]),
+                            r["sigma"], label)
+        else:
+            compare(host(r["out"]), want, cls, label, polar=polar)
 
 
 def test_batch_equals_plain_calls_and_shapes(ctx, zg):

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 from oracle import coracle as orc
-from parity import compare
+from parity import compare_mutated
 
 pytestmark = pytest.mark.gpu
 
@@ -38,14 +38,23 @@ def _check(ctx, zg, P, F, k, seed, stream, gen, rate, sigma, lo, hi):
     assert np.array_equal(W, Wo)
     # copied genes (cls 255) compare as fast-path values: bit for bit
     c = np.where(cls == 255, 0, cls).astype(np.uint8)
-    compare(C.ravel(), Co.ravel(), c.ravel(), ("ea", P.shape, k, gen))
+    pop, genes = P.shape
+
+    def z_of(idx):
+        # the oracle's variate of each gene: index (gen pop + c) genes + g of stream + 2
+        w = (gen * pop + idx // genes) * genes + idx % genes
+        return np.array([orc.fill_f64(orc.SM64, seed, stream + 2, int(v), 1)[0][0] for v in w])
+
+    compare_mutated(C.ravel(), Co.ravel(), c.ravel(), z_of, sigma, ("ea", P.shape, k, gen))
     assert ctx.zg_error_flags() == 0
 
 
 @pytest.mark.parametrize("pop,genes,k,gen,rate,sigma,lo,hi,nanfit", [
     (37, 70, 2, 3, 0.1, 0.5, -2.0, 2.0, False), (5, 1, 1, 0, 1.0, 3.0, -1.0, 1.0, False),
     (300, 129, 4, 7, 0.05, 0.1, -5.0, 5.0, True), (64, 64, 70, 1, 0.5, 1.0, -1.5, 1.5, True),
-    (4099, 33, 3, 100, 0.2, 0.7, -2.5, 2.5, False), (1, 1000, 5, 9, 0.3, 0.1, -5.0, 5.0, False)])
+    (4099, 33, 3, 100, 0.2, 0.7, -2.5, 2.5, False), (1, 1000, 5, 9, 0.3, 0.1, -5.0, 5.0, False),
+    (20000, 300, 2, 5, 0.05, 0.1, -5.0, 5.0, False), (50, 2048, 256, 2, 1.0, 0.2, -3.0, 3.0, True),
+    (9000, 513, 8, 1, 0.9, 0.3, -4.0, 4.0, False)])
 def test_ea_step_matches_oracle(ctx, zg, pop, genes, k, gen, rate, sigma, lo, hi, nanfit):
     rng = np.random.Generator(np.random.PCG64(pop + genes))
     P = rng.uniform(-2, 2, (pop, genes))

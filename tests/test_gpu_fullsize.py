@@ -16,7 +16,7 @@ import torch
 
 from oracle import coracle as orc
 from oracle import stats
-from parity import compare
+from parity import compare, compare_mutated, mutation_z
 
 pytestmark = pytest.mark.gpu
 
@@ -204,4 +204,4 @@ def test_c4_full_parity_batch(ctx, zg):
     xm = x.cpu().numpy()
     want, cls, errs = orc.mutate(x0, orc.SM64, 999, 0, 0, 0.1)
     assert errs == 0
-    compare(xm, want, cls, "c4 mutation")
+    compare_mutated(xm, want, cls, mutation_z(orc, orc.SM64, 999, 0, 0), 0.1, "c4 mutation")

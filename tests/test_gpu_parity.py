@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from oracle import coracle as orc
-from parity import compare
+from parity import compare, compare_mutated, mutation_z
 
 pytestmark = pytest.mark.gpu
 
@@ -131,7 +131,7 @@ def test_mutate(ctx, zg, n, kind, offset):
     ctx.zg_mutate(x, 0.1, kind=kind, seed=17, stream=2, first_index=10)
     got = host(x)
     want, cls, _ = orc.mutate(x0, kind, 17, 2, 10, 0.1)
-    compare(got, want, cls, ("mutate", n))
+    compare_mutated(got, want, cls, mutation_z(orc, kind, 17, 2, 10), 0.1, ("mutate", n))
 
 
 def test_decide_words_boundaries(ctx, zg):
@@ -245,7 +245,8 @@ def test_queue_overflow_path(ctx, zg, qcap):
         x.copy_(torch.from_numpy(x0))
         ctx.zg_mutate(x, 0.25, kind=1, seed=3, stream=1, first_index=0)
         want, cls, _ = orc.mutate(x0, 1, 3, 1, 0, 0.25)
-        compare(host(x), want, cls, ("overflow mutate", qcap))
+        compare_mutated(host(x), want, cls, mutation_z(orc, 1, 3, 1, 0), 0.25,
+                        ("overflow mutate", qcap))
     finally:
         for c, t in saved.items():
             ctx.zg_set_tune(c, *t)
