@@ -5,9 +5,9 @@
  * The method is the one the paper studies (Section 1 and Section 2,
  * "Ziggurat"): the 128-layer equal-area ziggurat of Marsaglia-Tsang 2000 /
  * Leong 2005 as implemented in GSL, which the paper ports to Java.  The
- * paper's statement of the problem is "a Gaussian from a given PRNG
- * instance" (Listing 2, nextGaussian(random)); here a PRNG instance is the
- * tuple (kind, seed, stream id, counter), and the bulk call fills n normals.
+ * paper's problem is drawing one normal variate from a given generator
+ * object (Listing 2, nextGaussian(random)); here a generator is the tuple
+ * (kind, seed, stream id, counter), and the bulk call fills n normals.
  *
  * Conventions for every entry point:
  *  - Every call returns a zg_status (ZG_OK == 0, errors < 0).  No exception
@@ -23,6 +23,9 @@
  *    zg_mutate.
  *  - Variates are index-keyed: variate v of stream s is a pure function of
  *    (kind, seed, s, v), whatever the launch geometry, batch or call split.
+ *  - The plain generation calls (zg_fill, zg_fill_streams, zg_mutate,
+ *    zg_ea_step) allocate nothing and issue no memset: a caller may capture
+ *    them in a HIP graph on hip_stream and replay it.
  *
  * Uniform sources (Section 2 measures both classes):
  *  - ZG_SPLITMIX64: the generator of SplittableRandom.  Word of draw d of
