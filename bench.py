@@ -7,7 +7,9 @@ of 4096 variates, written to one contiguous float64 buffer (2 GiB).  A step is
 one ziggurat fill of the whole buffer; the polar fill is timed the same way and
 reported beside it.  Inputs are synthetic (seeds only).
 
-Prints one JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 exits: the benchmark runs on one GPU (every
+variate is a pure function of its key, so GPUs would split the streams with no
+communication; that path is a design, not code).
 """
 import argparse
 import json
@@ -453,7 +455,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: every configuration here fits one MI355X, "
-              "and the path shards by index range with no communication (see the design notes)",
+              "and the path would shard by index range with no communication",
               file=sys.stderr)
         sys.exit(2)
     import torch
