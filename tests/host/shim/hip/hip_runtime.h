@@ -51,7 +51,12 @@ inline hipError_t hipDeviceGetAttribute(int *v, int, int) {
   *v = e ? std::atoi(e) : 256;
   return 0;
 }
-inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *o, const void *, int, size_t) { *o = 1; return 0; }
+// workgroups per compute unit that fit: EMU_OCC from the environment (default 1)
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *o, const void *, int, size_t) {
+  const char *e = std::getenv("EMU_OCC");
+  *o = e ? std::atoi(e) : 1;
+  return 0;
+}
 
 // ---- collectives
 struct EmuWave {

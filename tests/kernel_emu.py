@@ -37,8 +37,8 @@ def build(dst, seq_windows=None):
     return exe
 
 
-def run(exe, args, cus=None, timeout=600):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+def run(exe, args, cus=None, timeout=600, env=None):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", **(env or {}))
     if cus is not None:
         env["EMU_CUS"] = str(cus)
     return subprocess.run([exe, *[str(a) for a in args]], capture_output=True, text=True,

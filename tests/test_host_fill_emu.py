@@ -94,3 +94,23 @@ def test_fill_kernels_equal_oracle(emu, orc, case):
     bits = np.uint32 if op == 1 else np.uint64
     same = got.view(bits) == want.view(bits)
     assert same.all(), (int((~same).sum()), np.flatnonzero(~same)[:10])
+
+
+@pytest.mark.parametrize("waves,drain,res", [(2, 4, 1), (6, 3, 3), (4, 1, 8)],
+                         ids=["two-waves-drain-clamped", "six-waves", "four-waves-eight-per-cu"])
+def test_ws_fill_small_workgroups_equal_oracle(emu, orc, waves, drain, res):
+    """The wave-specialised fill in workgroups of 2 to 6 waves (drain waves
+    clamped to leave one streaming wave), 1, 3 or 8 per compute unit (the
+    stand-in reports room for 8): the same bits as the oracle."""
+    d, exe = emu
+    n_per, ns = 333, 301
+    out = os.path.join(d, f"out_ws_{waves}_{drain}_{res}.bin")
+    env = dict(EMU_WAVES=str(waves), EMU_RES=str(res), EMU_OCC="8")
+    r = kernel_emu.run(exe, ["fill", 0, 1, 99, 17, ns, n_per, 5, 1, drain, 2, out, "-"], cus=3,
+                       env=env)
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert "flags=0" in r.stderr, r.stderr
+    got = np.fromfile(out, dtype=np.float64)
+    want, _cls, errs = orc.fill_streams_f64(1, 99, 17, ns, 5, n_per)
+    assert errs == 0
+    assert got.view(np.uint64).tolist() == want.view(np.uint64).tolist()
