@@ -554,9 +554,10 @@ zg_status zg_set_tune(zg_ctx *ctx, int cls, const zg_tune *in) {
   if (in->group_steps != 1 && in->group_steps != 2 && in->group_steps != 4 && in->group_steps != 8)
     return ZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
+  // A slot's graphs are rebuilt by the next launch whose plan has another
+  // shape (the plan records it); they are not touched here, where another
+  // thread may be launching them.
   ctx->tune[cls] = *in;
-  if (cls == ZG_TUNE_BATCH)
-    for (auto &s : ctx->slots) s.invalidate_graphs();
   return ZG_OK;
 }
 

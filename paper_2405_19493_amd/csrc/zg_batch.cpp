@@ -43,11 +43,12 @@ zg_status plan_batch(zg_ctx *ctx, const zg_request *reqs, uint32_t nreq,
   plan->index.clear();
   plan->items.clear();
   plan->total_elems = 0;
-  const zg_tune bt = ctx->tune[ZG_TUNE_BATCH];
-  plan->bt = bt;
   std::unordered_map<int32_t, size_t> last_of;   // handle -> planned index of its last request
   std::unordered_map<int32_t, uint64_t> off_of;  // handle -> running offset
   std::lock_guard<std::mutex> lk(ctx->mu);
+  // the shape is read under the lock that zg_set_tune writes it under
+  const zg_tune bt = ctx->tune[ZG_TUNE_BATCH];
+  plan->bt = bt;
   for (uint32_t i = 0; i < nreq; ++i) {
     const zg_request &r = reqs[i];
     if (r.op != ZG_OP_FILL && r.op != ZG_OP_MUTATE) return ZG_EINVAL;
