@@ -424,9 +424,11 @@ def read_profile(kernel):
     return ent
 
 
-# VALU issue peak: one wave-64 instruction per 4 cycles per SIMD (a 16-lane
-# SIMD; FP64 and 64-bit integer work, the bulk of these kernels, run at that
-# rate), 256 CUs x 4 SIMDs at 2.4 GHz
+# VALU issue peak for FP64-heavy code: one wave-64 instruction per 4 cycles
+# per SIMD (the published FP64 vector rate, 16 lanes per cycle), 256 CUs x 4
+# SIMDs at 2.4 GHz.  Plain 32-bit integer instructions issue faster (about 2.6
+# cycles measured) and 32-bit multiplies slower (about 4.8), so for integer
+# work this is an estimate, not a ceiling.
 VALU_PEAK_G = 256 * 4 * 2.4e9 / 4 / 1e9
 
 

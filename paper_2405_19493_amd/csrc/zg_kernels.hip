@@ -1270,6 +1270,35 @@ DEV void ws_group(const Job &J, WsLds &L, const DevTables *T, const LaneConst &L
     double x[4];
     float xf[4];
     uint32_t b4;
+    if (ec + 2 * BSTEP <= ge && (!multi || rr + 2 * BSTEP <= J.n_per)) {
+      // two whole steps of one stream: both steps' words are computed before
+      // either step's stores, so their hash chains overlap
+      const uint64_t vc = J.first + rr;
+      if (KIND == ZG_JAVA_LCG48 && !have) {
+        Sc = lcg_jump(&T->lcg, lcg_state0(J.seed), 2 * lcg_index(s, vc, 0) + 1);
+        have = true;
+      }
+      double x2[4];
+      float xf2[4];
+      b4 = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec, ge, s, vc, Sc, x, xf);
+      if (KIND == ZG_JAVA_LCG48) Sc = aff(T->lcg.jump[1][2], Sc);
+      const uint32_t b4b = step_regs<OP, KIND, true>(J, L.t.f64, L.t.f32, T, LC, ec + BSTEP, ge, s,
+                                                     vc + BSTEP, Sc, x2, xf2);
+      if (KIND == ZG_JAVA_LCG48) Sc = aff(T->lcg.jump[1][2], Sc);
+      step_store<OP, true>(J, ec, ge, x, xf);
+      step_store<OP, true>(J, ec + BSTEP, ge, x2, xf2);
+      bits |= (b4 | b4b << 4) << (4 * sub);
+      ec += BSTEP;
+      ++sub;
+      rr += 2 * BSTEP;
+      if (multi)
+        while (rr >= J.n_per) {
+          rr -= J.n_per;
+          ++s;
+          have = false;
+        }
+      continue;
+    }
     const bool full = ec + BSTEP <= ge;
     if (!multi || rr + BSTEP <= J.n_per) {
       const uint64_t vc = J.first + rr;
