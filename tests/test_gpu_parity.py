@@ -252,14 +252,18 @@ def test_queue_overflow_path(ctx, zg, qcap):
             ctx.zg_set_tune(c, *t)
 
 
-@pytest.mark.parametrize("cls_t,tdt", [(0, torch.float64), (1, torch.float32), (3, torch.float64)])
-def test_launch_shape_never_changes_bits(ctx, zg, cls_t, tdt):
+@pytest.mark.parametrize("cls_t,tdt,kind", [(0, torch.float64, 1), (1, torch.float32, 1),
+                                            (3, torch.float64, 1), (0, torch.float64, 2)])
+def test_launch_shape_never_changes_bits(ctx, zg, cls_t, tdt, kind):
     """One workgroup per tile or a persistent grid, small or large tiles,
     4 to 16 waves, 1 to 8 steps per group, the block-pooled or the
     wave-specialised kernel with 1 to 8 drain waves, workgroups of 2 to 16
     waves (down to one streaming wave) and up to 8 per compute unit: the same
-    bits (every variate is keyed by its index)."""
+    bits (every variate is keyed by its index).  Streams of 777 (SplitMix64)
+    or 1001 (Java LCG, at most 256 streams) variates start inside steps, so
+    steps taken singly, in pairs and across stream ends all occur."""
     n = 3 * 65536 + 4097
+    n_per = 777 if kind == 1 else 1001
     saved = ctx.zg_get_tune(cls_t)
     rng = np.random.Generator(np.random.PCG64(12))
     x0 = torch.from_numpy(rng.uniform(-1, 1, n)).cuda() if cls_t == 3 else None
@@ -277,8 +281,9 @@ def test_launch_shape_never_changes_bits(ctx, zg, cls_t, tdt):
                 out.copy_(x0)
                 ctx.zg_mutate(out, 0.5, kind=1, seed=2, stream=7, first_index=33)
             else:
-                ctx.zg_fill_streams(out, 777, n // 777, kind=1, seed=2, stream0=7, first_index=33)
-                out = out[: (n // 777) * 777]
+                ctx.zg_fill_streams(out, n_per, n // n_per, kind=kind, seed=2, stream0=7,
+                                    first_index=33)
+                out = out[: (n // n_per) * n_per]
             got = host(out).tobytes()
             if ref is None:
                 ref = got
