@@ -249,7 +249,10 @@ def sequential_row(ctx, Z, torch, steps, warmup):
             "value": n / (ms * 1e-3), "unit": "variates/s", "ms": ms,
             "roofline": {"bound": "hbm", "achieved": 8.0 * n / (ms * 1e-3) / 1e9,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": 8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+                         "frac": 8.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         # the path is several launches (chain maps, scan, write pass),
+                         # timed as a whole; no counter pass covers it
+                         "kernel": "zg_fill_sequential (all its launches)", "traffic": None}}
 
 
 def f32_row(ctx, Z, torch, steps, warmup):
